@@ -1,0 +1,28 @@
+"""Build step for the oracle library (oracle/libhx_oracle.so).
+
+Test infrastructure: the oracle is compiled with plain gcc, -O2, no fast-math
+and no FP contraction, so that every double operation is the one written in
+edge_oracle.c.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libhx_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(HERE, "edge_oracle.c")
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-pthread",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+           src, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
