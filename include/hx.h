@@ -1,0 +1,248 @@
+/*
+ * hx.h -- C ABI of libhx.so, an MI355X (gfx950) implementation of the EDGE
+ * edge-detection pipeline evaluated in "Hercules: A Compiler for Productive
+ * Programming of Heterogeneous Systems" (Evaluation: the EDGE benchmark;
+ * Use and Impact of Schedules: EDGE's max_gradient reduction tree).
+ *
+ * The pipeline is nested parallel loops plus one associative reduction, as
+ * the paper's fork-join statement of a program has them ("Representing
+ * Parallelism with Fork-Joins"):
+ *   fork over [H, W]:  B = Gaussian blur of I          (k x k, clamped)
+ *   fork over [H, W]:  L = 5-point Laplacian of B
+ *   fork over [H, W]:  Z = 3x3 zero crossing of L (1 where signs differ)
+ *   fork over [H, W]:  G = Sobel magnitude of B
+ *   reduce  (monoid max over [H, W]):  M = max G
+ *   fork over [H, W]:  mask = Z and G > thresh_frac * M   (uint8, 0 or 1)
+ * Every stage reads its input at clamped coordinates.  The batched call
+ * adds an outer fork over images whose factors differ per image.
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an hx_status and never throws.  On any validation
+ *    failure nothing is enqueued and the call returns HX_E_INVALID (or
+ *    HX_E_UNSUPPORTED); hx_last_error() then describes the problem.
+ *  - Pointers named d_* or inside hx_image are DEVICE pointers on the
+ *    pipeline's device; h_* are host pointers.  The caller owns them and
+ *    must keep them alive until the enqueued work on `stream` completes.
+ *  - Work is enqueued on `stream` (0 = the null stream) and the call
+ *    returns without waiting.  Device-side failures (a kernel that could
+ *    not launch) return HX_E_HIP; asynchronous faults surface at the next
+ *    call or synchronisation.
+ *  - The input is never written.  Every output element is written.
+ *  - Pipelines and servers are not thread-safe unless stated (hx_serve_*
+ *    are thread-safe).  hx_last_error() is thread-local.
+ *  - Inputs must be finite fp32; masks are written as 0 or 1.
+ */
+#ifndef HX_H
+#define HX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same opaque type as the HIP runtime's; a repeated identical typedef is
+ * valid C11 and C++. */
+typedef struct ihipStream_t* hipStream_t;
+
+typedef enum {
+    HX_OK = 0,
+    HX_E_INVALID = 1,      /* bad argument; nothing enqueued            */
+    HX_E_NOMEM = 2,        /* device or pinned host allocation failed   */
+    HX_E_HIP = 3,          /* a HIP runtime call failed                 */
+    HX_E_UNSUPPORTED = 4,  /* valid request this build cannot run       */
+    HX_E_BUSY = 5,         /* server: request would never fit budget    */
+    HX_E_PENDING = 6,      /* server: ticket not finished yet           */
+    HX_E_NOT_FOUND = 7     /* server: unknown or already-collected id   */
+} hx_status;
+
+typedef struct hx_pipeline hx_pipeline;
+typedef struct hx_server hx_server;
+
+/* Pass structure of the fused (fusion_depth 4) pipeline.  The max must be
+ * known before any mask bit can be written, so the work splits in two:
+ *  STORE:      pass 1 computes every stage and stores one float per pixel
+ *              (G^2 where Z = 1, else -1) plus the max; pass 2 thresholds.
+ *  RECOMPUTE:  pass 1 computes blur and Sobel only, for the max; pass 2
+ *              recomputes every stage and writes the mask directly. */
+enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2 };
+
+/* Shape of the max reduction (the paper's reduction_tree schedule and its
+ * warp-primitive refinement, Use and Impact of Schedules):
+ *  TREE:        per-lane max, wave64 shuffle tree, one atomic per wave.
+ *  TWO_LEVEL:   per-thread partial maxima written out, then one thread per
+ *               image combines them serially (a tree without wave
+ *               primitives).
+ *  SEQUENTIAL:  one thread per image scans every G value (no tree).
+ * TWO_LEVEL and SEQUENTIAL exist for the ablation; they need
+ * fusion_depth 1. */
+enum { HX_REDUCE_TREE = 0, HX_REDUCE_TWO_LEVEL = 1, HX_REDUCE_SEQUENTIAL = 2 };
+
+/* A schedule: the knobs the autotuner searches (the role of the paper's
+ * fork-tile / fork-chunk / fusion / fission schedules).
+ *  fusion_depth 1: one kernel per stage (blur, Laplacian, zero crossing,
+ *                  Sobel + max, threshold); tile_w x tile_h is the pixel
+ *                  tile of one 256-thread workgroup, tile_w in {16,32,64},
+ *                  tile_h in {16,32}.
+ *  fusion_depth 2: [blur, Sobel + max] [Laplacian, zero crossing] [threshold]
+ *  fusion_depth 3: [blur, Sobel + max, Laplacian] [zero crossing] [threshold]
+ *  fusion_depth 4: all stencil stages in one pass (see pass_mode).
+ *  For depth 2..4 the first kernel is a register sweep: each wave64 owns a
+ *  strip of tile_w input columns (64, 128 or 256: 1, 2 or 4 per lane) and
+ *  walks tile_h rows (16, 32, 64 or 128) down it. */
+typedef struct {
+    int32_t tile_w, tile_h, fusion_depth, pass_mode, reduce_mode;
+} hx_schedule;
+
+/* Pipeline parameters: the constants of the computation plus the "dynamic
+ * constants" (Collections and Dynamic Constants) that size every scratch
+ * buffer once, at creation.  Zero fields take defaults: ksize 5,
+ * sigma 1.0, thresh_frac 0.1, schedule from the autotuner cache or the
+ * built-in default, max_pixels 2^25, max_images 1024. */
+typedef struct {
+    int32_t ksize;            /* odd, 1..15; fused kernels need 3, 5 or 7 */
+    float sigma;              /* > 0                                       */
+    float thresh_frac;        /* theta in tau = theta * M, in [0, 1]       */
+    int32_t tile_w, tile_h, fusion_depth, pass_mode;  /* 0 = automatic    */
+    int64_t max_pixels;       /* max sum of H*W over one call            */
+    int64_t max_images;       /* max images in one batched call          */
+} hx_params;
+
+/* One image: device pointers.  src is H rows of `width` fp32 values with a
+ * row pitch of src_pitch elements (>= width); mask is H rows of `width`
+ * bytes with a row pitch of mask_pitch bytes (>= width). */
+typedef struct {
+    const float* src;
+    int64_t height, width, src_pitch;
+    uint8_t* mask;
+    int64_t mask_pitch;
+} hx_image;
+
+/* Create a pipeline on `device`.  Allocates all fixed scratch (per-image
+ * max slots, counters, the batch descriptor table and its pinned staging
+ * copy).  Buffers whose size depends on the images (the pass-1 store
+ * buffer, the stage buffers of fusion depths 1..3, the descriptor table)
+ * are allocated by the first call that needs them and grow when a later
+ * call needs more; warm a pipeline up before capturing its calls in a
+ * graph.
+ * Returns HX_E_INVALID for bad parameters, HX_E_NOMEM / HX_E_HIP on
+ * allocation or device errors.  *out is set only on HX_OK. */
+hx_status hx_pipeline_create(const hx_params* params, int device,
+                             hx_pipeline** out);
+
+/* Wait for the pipeline's outstanding work, release its memory.  NULL is a
+ * no-op. */
+void hx_pipeline_destroy(hx_pipeline* p);
+
+/* Wait until every call enqueued on this pipeline has finished (the whole
+ * device is synchronised).  Returns HX_E_HIP if the device reported an
+ * error. */
+hx_status hx_pipeline_sync(hx_pipeline* p);
+
+/* Force a schedule for every later call (NULL restores automatic choice).
+ * HX_E_INVALID for knob values outside the sets documented above,
+ * HX_E_UNSUPPORTED for a fused depth with ksize not in {3,5,7}. */
+hx_status hx_pipeline_set_schedule(hx_pipeline* p, const hx_schedule* s);
+
+/* The schedule a call on an H x W image would use right now. */
+hx_status hx_pipeline_get_schedule(const hx_pipeline* p, int64_t height,
+                                   int64_t width, hx_schedule* out);
+
+/* One image, the per-image form: a handful of kernel launches on `stream`.
+ * d_max (device, nullable) receives M = max G as one float. */
+hx_status hx_edge_detect(hx_pipeline* p, const hx_image* img, float* d_max,
+                         hipStream_t stream);
+
+/* n images of any sizes in ONE graph launch (captured once, replayed for
+ * every call): a reset of the per-image max slots, then one persistent
+ * kernel over the flattened list of (image, tile) pass-1 items, then one
+ * over the (image, row-run or tile) pass-2 items.  No workgroup waits on
+ * another; the kernel boundary makes each image's max final before its
+ * mask is written.  imgs is a HOST array of n descriptors (device pointers
+ * inside); it is copied before the call returns.  d_max (device,
+ * nullable) receives n floats.  Requires 1 <= n <= max_images and
+ * sum H*W <= max_pixels.  Each image's result is bit-identical to
+ * hx_edge_detect on it alone.  Batched calls on different streams use
+ * separate scratch (up to six in flight per pipeline). */
+hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs,
+                                 int32_t n, float* d_max, hipStream_t stream);
+
+/* Test hook: the fusion-depth-1 pipeline on one image with every stage
+ * written out.  d_B, d_L, d_G: dense H*W floats (G is the magnitude);
+ * d_Z: dense H*W bytes; d_max: one float (M); the mask goes to img->mask.
+ * Any of d_B, d_L, d_Z, d_G may be NULL. */
+hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img,
+                                float* d_B, float* d_L, uint8_t* d_Z,
+                                float* d_G, float* d_max, hipStream_t stream);
+
+/* Time every candidate schedule on a synthetic H x W image on this
+ * pipeline's device (blocking; allocates and frees its own test image),
+ * keep the fastest for that shape class, and append it to the JSON cache
+ * at cache_path (NULL = do not persist).  Later calls on images of the
+ * same shape class use it unless a schedule is forced. */
+hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
+                      const char* cache_path);
+
+/* Load schedules from a cache written by hx_autotune (entries for other
+ * ksize values or devices are ignored). */
+hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path);
+
+/* ------------------------------------------------------------ serving --
+ * A request loop with continuous batching.  Requests are admitted while
+ * their device buffers fit in the HBM budget, copied to the device, and
+ * every admitted request not yet launched joins the next batch; batches
+ * run on `streams` round-robin compute streams so they overlap on the
+ * device.  All hx_serve_* calls are thread-safe. */
+typedef struct {
+    size_t hbm_budget;     /* bytes of arena a request set may occupy     */
+    int32_t streams;       /* concurrent compute streams (1..8)           */
+    int32_t max_batch;     /* images per launched batch (<= max_images)   */
+} hx_serve_params;
+
+/* d_arena/arena_bytes: one caller-owned device allocation (e.g. a torch
+ * uint8 tensor) that the server sub-allocates request buffers from; the
+ * effective budget is min(hbm_budget, arena_bytes).  The server owns a
+ * scheduler thread and its streams; the pipeline must outlive it and must
+ * not be used by anyone else meanwhile. */
+hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp,
+                          void* d_arena, size_t arena_bytes, hx_server** out);
+
+/* Enqueue one request.  h_src: host fp32 image, h rows of w values, row
+ * pitch `pitch` elements; it is copied before the call returns.
+ * arrival_s: the request's scheduled arrival time on the server's clock
+ * (hx_serve_now), used for latency.  HX_E_BUSY if the request alone can
+ * never fit the budget. */
+hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h,
+                          int64_t w, int64_t pitch, double arrival_s,
+                          uint64_t* ticket);
+
+/* Collect a finished request: copies its mask into h_mask (row pitch
+ * mask_pitch bytes) and its latency (completion minus arrival, seconds)
+ * into *latency_s (nullable).  HX_OK done (the ticket is then released),
+ * HX_E_PENDING not yet, HX_E_NOT_FOUND unknown ticket, HX_E_HIP if the
+ * server hit a device error. */
+hx_status hx_serve_poll(hx_server* s, uint64_t ticket, uint8_t* h_mask,
+                        int64_t mask_pitch, double* latency_s);
+
+/* Seconds on the server's monotonic clock. */
+double hx_serve_now(const hx_server* s);
+
+/* Counters since creation: requests completed, batches launched, pixels
+ * processed, peak arena bytes in use.  Any pointer may be NULL. */
+hx_status hx_serve_stats(const hx_server* s, uint64_t* completed,
+                         uint64_t* batches, uint64_t* pixels,
+                         uint64_t* peak_bytes);
+
+/* Drain every admitted request, stop the scheduler, free the server. */
+hx_status hx_serve_destroy(hx_server* s);
+
+/* ------------------------------------------------------------ errors --- */
+const char* hx_status_str(hx_status s);
+const char* hx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HX_H */

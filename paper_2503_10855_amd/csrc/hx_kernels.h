@@ -1,0 +1,126 @@
+// hx_kernels.h -- argument blocks and launchers of the HIP kernels.
+// Internal to libhx.so (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hx_device.h"
+
+namespace hx {
+
+// Sweep modes: which stages the register sweep computes and what it writes.
+enum SweepMode : int {
+    SM_STORE = 0,    // every stage -> pass-1 code (G^2 if Z else -1) + max
+    SM_MAXONLY = 1,  // blur + Sobel -> max only
+    SM_MASK = 2,     // every stage -> mask (reads the finished max)
+    SM_BG = 3,       // blur + Sobel -> B, G^2, max
+    SM_BGL = 4,      // blur + Sobel + Laplacian -> L, G^2, max
+};
+
+// One image as the kernels see it.  Pitches are in elements of the
+// respective buffer.  fout: pass-1 code (STORE), B (BG) or L (BGL);
+// g2: G^2 (BG, BGL).  fout/g2 rows use pitch `op`, which is a multiple of
+// 4 floats with 16-byte aligned rows.
+struct ImgArgs {
+    const float* src;
+    int64_t sp;
+    uint8_t* mask;
+    int64_t mp;
+    float* fout;
+    float* g2;
+    int64_t op;
+    uint32_t* slot;   // max G^2 bits of this image
+    float* dmax;      // optional: receives M = sqrt(max G^2)
+    int32_t H, W;
+};
+
+// Geometry of a register-sweep tile (one wave64): C input columns per lane,
+// TY output rows; KS the blur size.
+struct SweepGeom {
+    int ks, c, ty;
+    int halo() const { return ks / 2 + 2; }
+    int hl() const { return ((halo() + c - 1) / c) * c; }
+    int sw() const { return 64 * c; }
+    int ow() const { return ((sw() - hl() - halo()) / c) * c; }
+    int64_t strips(int64_t W) const { return (W + ow() - 1) / ow(); }
+    int64_t bands(int64_t H) const { return (H + ty - 1) / ty; }
+    int64_t tiles(int64_t H, int64_t W) const { return strips(W) * bands(H); }
+};
+
+// Is (ks, c, ty) one of the compiled sweep shapes?
+bool sweep_supported(int ks, int c, int ty);
+
+// ---- per-image launchers (return hipSuccess or the launch error) -------
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_sweep(int mode, int ks, int c, int ty, const ImgArgs& a,
+                        const Taps& t, float theta, hipStream_t s);
+// Pass 2 of STORE: code -> mask, and M into dmax.
+hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s);
+// Write M into a.dmax from a.slot (one thread).
+hipError_t launch_write_max(const ImgArgs& a, hipStream_t s);
+
+// Depth-1 stage kernels (tile tw x th pixels per 256-thread workgroup).
+struct StageBufs {
+    float* B;        // dense-pitched H x op
+    float* L;
+    float* G2;
+    uint8_t* Z;      // pitch op bytes
+    float* partial;  // TWO_LEVEL: per-thread partial maxima
+    int64_t op;
+};
+hipError_t launch_blur(const ImgArgs& a, const StageBufs& b, const Taps& t,
+                       int ks, int tw, int th, hipStream_t s);
+hipError_t launch_laplacian(const ImgArgs& a, const StageBufs& b, int tw,
+                            int th, hipStream_t s);
+hipError_t launch_zero_cross(const ImgArgs& a, const StageBufs& b,
+                             const float* Lsrc, int tw, int th, hipStream_t s);
+// reduce_mode: HX_REDUCE_* from hx.h.  For TWO_LEVEL and SEQUENTIAL this
+// also launches the final combining kernel.
+hipError_t launch_sobel_max(const ImgArgs& a, const StageBufs& b, int tw,
+                            int th, int reduce_mode, hipStream_t s);
+// Depth-2 second kernel: L from B, then Z.
+hipError_t launch_lap_zero_cross(const ImgArgs& a, const StageBufs& b, int tw,
+                                 int th, hipStream_t s);
+// Final threshold of depths 1-3: (Z, G^2, max) -> mask, M into dmax.
+hipError_t launch_threshold_zg(const ImgArgs& a, const StageBufs& b,
+                               float theta, int tw, int th, hipStream_t s);
+// Test hook: G = sqrt(G^2) and B, L, Z copied out densely (pitch W).
+hipError_t launch_export_stages(const ImgArgs& a, const StageBufs& b,
+                                float* dB, float* dL, uint8_t* dZ, float* dG,
+                                hipStream_t s);
+
+// ---- batched launch ----------------------------------------------------
+// Device descriptor table of one batched call: BatchHeader, then n_images
+// ImgArgs, then n_items1 pass-1 items, then n_items2 pass-2 items.
+struct BatchItem {
+    int32_t image;   // index into the ImgArgs array
+    int32_t local;   // pass 1: sweep tile; pass 2: row run (STORE) or tile
+};
+struct BatchHeader {
+    int32_t n_images;
+    int32_t n_items1;
+    int32_t n_items2;
+    int32_t pass_mode;  // HX_PASS_STORE / HX_PASS_RECOMPUTE
+    float theta;
+    int32_t pad[3];
+};
+
+size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2);
+int batch_sweep_c();   // columns per lane of the batch sweep
+int batch_sweep_ty();  // rows per batch sweep tile
+// Rows per pass-2 item of the STORE threshold for width W.
+int batch_p2_rows(int64_t W);
+// Zero the first n (read from the table) max slots; grid sized for
+// max_images.
+hipError_t launch_batch_reset(const void* d_table, uint32_t* slots,
+                              int max_images, hipStream_t s);
+// One pass (phase 1 or 2) over the table's item list on `grid` persistent
+// workgroups.
+hipError_t launch_batch_phase(int ks, int pass_mode, int phase,
+                              const void* d_table, const Taps& t, int grid,
+                              hipStream_t s);
+// Workgroups of a phase kernel that fit on the device at once; 0 on error.
+int batch_grid_size(int device, int ks, int pass_mode, int phase);
+
+}  // namespace hx

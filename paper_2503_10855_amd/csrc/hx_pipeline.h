@@ -1,0 +1,115 @@
+// hx_pipeline.h -- host-side state behind the hx_pipeline handle.
+// Internal to libhx.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/hx.h"
+#include "hx_kernels.h"
+
+namespace hx {
+
+// Thread-local error text behind hx_last_error().
+void set_error(const char* fmt, ...);
+hx_status fail(hx_status st, const char* fmt, ...);
+hx_status hip_fail(hipError_t e, const char* what);
+
+// Make `dev` current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1, dev;
+    explicit DeviceGuard(int d) : dev(d) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+    }
+};
+
+// A device buffer that grows on demand (growth frees and reallocates,
+// which waits for the device; it happens only the first time a larger
+// size is needed).
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need);
+    void release();
+};
+
+// Resources of one in-flight batched launch.  Batched calls rotate over a
+// few of these so launches on different streams never share scratch.
+struct BatchContext {
+    bool ready = false;
+    DevBuf table;               // device descriptor table (grows on demand)
+    void* h_table = nullptr;    // pinned staging copy of the table
+    size_t h_table_bytes = 0;
+    uint32_t* slots = nullptr;  // max_images max slots
+    DevBuf code;                // pass-1 store buffer
+    hipEvent_t ev_done = nullptr;
+    bool in_flight = false;
+    // Captured [reset, pass 1, pass 2] per pass mode, with the table
+    // address and grid sizes baked into the kernel nodes.
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    const void* graph_table[3] = {nullptr, nullptr, nullptr};
+};
+
+struct ShapeClass {
+    int hb, wb;  // floor(log2(H)), floor(log2(W))
+    bool operator<(const ShapeClass& o) const {
+        return hb != o.hb ? hb < o.hb : wb < o.wb;
+    }
+};
+ShapeClass shape_class(int64_t H, int64_t W);
+
+}  // namespace hx
+
+struct hx_pipeline {
+    int device = 0;
+    hx_params prm{};
+    hx::Taps taps{};
+    int cu_count = 0;
+
+    bool forced = false;
+    hx_schedule forced_sched{};
+    std::map<hx::ShapeClass, hx_schedule> tuned;
+
+    // Per-image scratch.
+    uint32_t* slot1 = nullptr;
+    hx::DevBuf code1, bufB, bufL, bufG2, bufZ, bufPart;
+
+    // Batched launches.
+    static constexpr int kContexts = 6;
+    hx::BatchContext ctx[kContexts];
+    int next_ctx = 0;
+    std::mutex batch_mu;  // guards context rotation (the server calls from
+                          // its own thread)
+    hipStream_t capture_stream = nullptr;
+    int batch_grid[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [pass mode][phase - 1]
+};
+
+namespace hx {
+
+// The schedule a call on an H x W image uses (forced > tuned > default),
+// with the pipeline's fixed knobs applied.
+hx_schedule choose_schedule(const hx_pipeline* p, int64_t H, int64_t W);
+hx_status validate_schedule(const hx_pipeline* p, const hx_schedule& s);
+hx_status validate_image(const hx_pipeline* p, const hx_image* img);
+
+// The per-image form with an explicit schedule (used by hx_edge_detect
+// and the autotuner).
+hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
+                    const hx_schedule& s, hipStream_t stream);
+// The batched form with an explicit pass mode.
+hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
+                      float* d_max, int pass_mode, hipStream_t stream);
+// Wait for a context's last launch.
+hx_status ctx_wait(BatchContext& c);
+
+}  // namespace hx

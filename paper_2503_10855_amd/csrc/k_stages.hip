@@ -1,0 +1,312 @@
+// k_stages.hip -- the unfused (fusion depth 1) stage kernels, the second
+// kernels of fusion depths 2 and 3, the threshold kernels and small
+// helpers.  One kernel per fork over pixels, in the form the paper's EDGE
+// schedule used (no fusion; Use and Impact of Schedules, transform table).
+// Per-pixel arithmetic comes from hx_device.h, identical to the sweeps.
+#include <hip/hip_runtime.h>
+
+#include "../../include/hx.h"
+#include "hx_kernels.h"
+#include "thresh_impl.h"
+
+namespace hx {
+
+namespace {
+
+// Pixel tile of a 256-thread workgroup: TW x TH pixels, thread (tx, ty0)
+// handles column tx of rows ty0, ty0 + 256/TW, ...
+struct TileMap {
+    int tw, th;
+    int tiles_x, tiles_y;
+};
+
+__device__ __forceinline__ bool tile_px(const TileMap& m, int k, int W, int H,
+                                        int& x, int& y) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = bid % m.tiles_x, by = bid / m.tiles_x;
+    const int rows_per = 256 / m.tw;
+    x = bx * m.tw + (int)(threadIdx.x % m.tw);
+    y = by * m.th + (int)(threadIdx.x / m.tw) + k * rows_per;
+    return (x < W) & (y < H) & ((int)(threadIdx.x / m.tw) + k * rows_per < m.th);
+}
+
+__device__ __forceinline__ int reps(const TileMap& m) {
+    const int rows_per = 256 / m.tw;
+    return (m.th + rows_per - 1) / rows_per;
+}
+
+__global__ __launch_bounds__(256) void k_blur(ImgArgs a, StageBufs b, Taps t,
+                                             int ks, TileMap m) {
+    const int r = ks / 2;
+    for (int k = 0; k < reps(m); ++k) {
+        int x, y;
+        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
+        float col[kMaxK];
+        for (int i = 0; i < ks; ++i) {
+            const float* rp = a.src + (int64_t)clampi(y - r + i, 0, a.H - 1) * a.sp;
+            float row[kMaxK];
+            for (int j = 0; j < ks; ++j) row[j] = rp[clampi(x - r + j, 0, a.W - 1)];
+            col[i] = blur_chain_rt(row, t, ks);
+        }
+        b.B[(int64_t)y * b.op + x] = blur_chain_rt(col, t, ks);
+    }
+}
+
+__device__ __forceinline__ float at(const float* X, int64_t op, int y, int x,
+                                    int H, int W) {
+    return X[(int64_t)clampi(y, 0, H - 1) * op + clampi(x, 0, W - 1)];
+}
+
+__device__ __forceinline__ float lap_at(const float* B, int64_t op, int y,
+                                        int x, int H, int W) {
+    const float ns = at(B, op, y - 1, x, H, W) + at(B, op, y + 1, x, H, W);
+    const float ew = at(B, op, y, x - 1, H, W) + at(B, op, y, x + 1, H, W);
+    return lap_from(ns, ew, at(B, op, y, x, H, W));
+}
+
+__global__ __launch_bounds__(256) void k_laplacian(ImgArgs a, StageBufs b,
+                                                  TileMap m) {
+    for (int k = 0; k < reps(m); ++k) {
+        int x, y;
+        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
+        b.L[(int64_t)y * b.op + x] = lap_at(b.B, b.op, y, x, a.H, a.W);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_cross(ImgArgs a, StageBufs b,
+                                                   const float* L, TileMap m) {
+    for (int k = 0; k < reps(m); ++k) {
+        int x, y;
+        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
+        float mx = -__builtin_inff(), mn = __builtin_inff();
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const float v = at(L, b.op, y + dy, x + dx, a.H, a.W);
+                mx = __builtin_fmaxf(mx, v);
+                mn = __builtin_fminf(mn, v);
+            }
+        b.Z[(int64_t)y * b.op + x] = zero_cross(mx, mn) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lap_zero_cross(ImgArgs a, StageBufs b,
+                                                       TileMap m) {
+    for (int k = 0; k < reps(m); ++k) {
+        int x, y;
+        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
+        float mx = -__builtin_inff(), mn = __builtin_inff();
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                // L at the clamped neighbour (each stage reads clamped).
+                const int yy = clampi(y + dy, 0, a.H - 1);
+                const int xx = clampi(x + dx, 0, a.W - 1);
+                const float v = lap_at(b.B, b.op, yy, xx, a.H, a.W);
+                mx = __builtin_fmaxf(mx, v);
+                mn = __builtin_fminf(mn, v);
+            }
+        b.Z[(int64_t)y * b.op + x] = zero_cross(mx, mn) ? 1 : 0;
+    }
+}
+
+__device__ __forceinline__ float g2_at(const float* B, int64_t op, int y,
+                                       int x, int H, int W) {
+    float dxr[3], syr[3];
+    for (int d = 0; d < 3; ++d) {
+        const int yy = clampi(y - 1 + d, 0, H - 1);
+        const float l = at(B, op, yy, x - 1, H, W);
+        const float r = at(B, op, yy, x + 1, H, W);
+        dxr[d] = sobel_dx(l, r);
+        syr[d] = sobel_sy(l + r, at(B, op, yy, x, H, W));
+    }
+    return sobel_g2(dxr[0], dxr[1], dxr[2], syr[0], syr[2]);
+}
+
+// reduce: 0 tree (wave shuffle + atomic), 1 per-thread partials.
+__global__ __launch_bounds__(256) void k_sobel(ImgArgs a, StageBufs b,
+                                              TileMap m, int reduce) {
+    float mx = 0.0f;
+    for (int k = 0; k < reps(m); ++k) {
+        int x, y;
+        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
+        const float g2 = g2_at(b.B, b.op, y, x, a.H, a.W);
+        b.G2[(int64_t)y * b.op + x] = g2;
+        mx = __builtin_fmaxf(mx, g2);
+    }
+    if (reduce == HX_REDUCE_TREE) {
+        mx = wave_max(mx);
+        if (lane_id() == 0) atomic_max_g2(a.slot, mx);
+    } else if (reduce == HX_REDUCE_TWO_LEVEL) {
+        b.partial[(int64_t)blockIdx.x * 256 + threadIdx.x] = mx;
+    }
+}
+
+// Final level of the TWO_LEVEL tree: one thread combines every partial,
+// in order (the paper's fission into a parallel and a serial fork).
+__global__ void k_combine_partials(ImgArgs a, const float* partial, int64_t n) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float mx = 0.0f;
+    for (int64_t i = 0; i < n; ++i) mx = __builtin_fmaxf(mx, partial[i]);
+    *a.slot = __float_as_uint(mx);
+}
+
+// SEQUENTIAL: one thread scans every G^2 value (no reduction tree).
+__global__ void k_sequential_max(ImgArgs a, const float* G2, int64_t op) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float mx = 0.0f;
+    for (int y = 0; y < a.H; ++y)
+        for (int x = 0; x < a.W; ++x) mx = __builtin_fmaxf(mx, G2[(int64_t)y * op + x]);
+    *a.slot = __float_as_uint(mx);
+}
+
+__global__ __launch_bounds__(256) void k_threshold_zg(ImgArgs a, StageBufs b,
+                                                     float theta, TileMap m) {
+    const uint32_t m2 = *a.slot;
+    const float thr2 = thr2_from(m2, theta);
+    if (a.dmax && blockIdx.x == 0 && threadIdx.x == 0) *a.dmax = max_from(m2);
+    for (int k = 0; k < reps(m); ++k) {
+        int x, y;
+        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
+        const int64_t i = (int64_t)y * b.op + x;
+        a.mask[(int64_t)y * a.mp + x] = (b.Z[i] && (b.G2[i] > thr2)) ? 1 : 0;
+    }
+}
+
+// Pass 2 of STORE on one image: code -> mask, 4 pixels per thread.
+__global__ __launch_bounds__(256) void k_threshold_code(ImgArgs a, float theta) {
+    const uint32_t m2 = *a.slot;
+    const float thr2 = thr2_from(m2, theta);
+    if (a.dmax && blockIdx.x == 0 && threadIdx.x == 0) *a.dmax = max_from(m2);
+    const int wq = (a.W + 3) / 4;
+    const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
+    const int64_t total = (int64_t)wq * a.H;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * 256) {
+        const int y = (int)(g / wq);
+        const int x = (int)(g - (int64_t)y * wq) * 4;
+        threshold4(a, y, x, thr2, mvec);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_write_max(ImgArgs a) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && a.dmax) *a.dmax = max_from(*a.slot);
+}
+
+__global__ __launch_bounds__(256) void k_export(ImgArgs a, StageBufs b,
+                                               float* dB, float* dL,
+                                               uint8_t* dZ, float* dG) {
+    const int64_t n = (int64_t)a.H * a.W;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const int y = (int)(i / a.W), x = (int)(i - (int64_t)y * a.W);
+        const int64_t j = (int64_t)y * b.op + x;
+        if (dB) dB[i] = b.B[j];
+        if (dL) dL[i] = b.L[j];
+        if (dZ) dZ[i] = b.Z[j];
+        if (dG) dG[i] = __builtin_sqrtf(b.G2[j]);
+    }
+}
+
+TileMap make_map(const ImgArgs& a, int tw, int th) {
+    TileMap m;
+    m.tw = tw;
+    m.th = th;
+    m.tiles_x = (a.W + tw - 1) / tw;
+    m.tiles_y = (a.H + th - 1) / th;
+    return m;
+}
+
+int grid_of(const TileMap& m) { return m.tiles_x * m.tiles_y; }
+
+int stream_grid(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g > 65536) g = 65536;
+    return g < 1 ? 1 : (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(stream_grid(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur(const ImgArgs& a, const StageBufs& b, const Taps& t,
+                       int ks, int tw, int th, hipStream_t s) {
+    const TileMap m = make_map(a, tw, th);
+    hipLaunchKernelGGL(k_blur, dim3(grid_of(m)), dim3(256), 0, s, a, b, t, ks, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_laplacian(const ImgArgs& a, const StageBufs& b, int tw,
+                            int th, hipStream_t s) {
+    const TileMap m = make_map(a, tw, th);
+    hipLaunchKernelGGL(k_laplacian, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_cross(const ImgArgs& a, const StageBufs& b,
+                             const float* Lsrc, int tw, int th, hipStream_t s) {
+    const TileMap m = make_map(a, tw, th);
+    hipLaunchKernelGGL(k_zero_cross, dim3(grid_of(m)), dim3(256), 0, s, a, b, Lsrc, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_lap_zero_cross(const ImgArgs& a, const StageBufs& b, int tw,
+                                 int th, hipStream_t s) {
+    const TileMap m = make_map(a, tw, th);
+    hipLaunchKernelGGL(k_lap_zero_cross, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_sobel_max(const ImgArgs& a, const StageBufs& b, int tw,
+                            int th, int reduce_mode, hipStream_t s) {
+    const TileMap m = make_map(a, tw, th);
+    hipLaunchKernelGGL(k_sobel, dim3(grid_of(m)), dim3(256), 0, s, a, b, m, reduce_mode);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (reduce_mode == HX_REDUCE_TWO_LEVEL) {
+        hipLaunchKernelGGL(k_combine_partials, dim3(1), dim3(64), 0, s, a,
+                           (const float*)b.partial, (int64_t)grid_of(m) * 256);
+        e = hipGetLastError();
+    } else if (reduce_mode == HX_REDUCE_SEQUENTIAL) {
+        hipLaunchKernelGGL(k_sequential_max, dim3(1), dim3(64), 0, s, a,
+                           (const float*)b.G2, b.op);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_threshold_zg(const ImgArgs& a, const StageBufs& b,
+                               float theta, int tw, int th, hipStream_t s) {
+    const TileMap m = make_map(a, tw, th);
+    hipLaunchKernelGGL(k_threshold_zg, dim3(grid_of(m)), dim3(256), 0, s, a, b, theta, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s) {
+    const int64_t work = (int64_t)((a.W + 3) / 4) * a.H;
+    hipLaunchKernelGGL(k_threshold_code, dim3(stream_grid(work, 256 * 4)), dim3(256), 0, s,
+                       a, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_max(const ImgArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_write_max, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_stages(const ImgArgs& a, const StageBufs& b,
+                                float* dB, float* dL, uint8_t* dZ, float* dG,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_export, dim3(stream_grid((int64_t)a.H * a.W, 256 * 8)), dim3(256),
+                       0, s, a, b, dB, dL, dZ, dG);
+    return hipGetLastError();
+}
+
+}  // namespace hx

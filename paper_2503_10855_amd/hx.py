@@ -1,0 +1,291 @@
+"""ctypes binding of libhx.so (include/hx.h).
+
+Argument marshalling only: every step of the pipeline runs in the HIP
+kernels behind the C ABI.  torch supplies device memory and streams.
+Importing this module loads libhx.so and raises ImportError if it has not
+been built (``python -m paper_2503_10855_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhx.so")
+
+HX_OK, HX_E_INVALID, HX_E_NOMEM, HX_E_HIP, HX_E_UNSUPPORTED, HX_E_BUSY, \
+    HX_E_PENDING, HX_E_NOT_FOUND = range(8)
+PASS_AUTO, PASS_STORE, PASS_RECOMPUTE = 0, 1, 2
+REDUCE_TREE, REDUCE_TWO_LEVEL, REDUCE_SEQUENTIAL = 0, 1, 2
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("ksize", ctypes.c_int32), ("sigma", ctypes.c_float),
+                ("thresh_frac", ctypes.c_float), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("fusion_depth", ctypes.c_int32),
+                ("pass_mode", ctypes.c_int32), ("max_pixels", ctypes.c_int64),
+                ("max_images", ctypes.c_int64)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("height", ctypes.c_int64),
+                ("width", ctypes.c_int64), ("src_pitch", ctypes.c_int64),
+                ("mask", ctypes.c_void_p), ("mask_pitch", ctypes.c_int64)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("fusion_depth", ctypes.c_int32), ("pass_mode", ctypes.c_int32),
+                ("reduce_mode", ctypes.c_int32)]
+
+    def astuple(self):
+        return (self.tile_w, self.tile_h, self.fusion_depth, self.pass_mode,
+                self.reduce_mode)
+
+
+class ServeParams(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_i32, _i64, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "hx_pipeline_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int,
+                                          ctypes.POINTER(_P)]),
+    "hx_pipeline_destroy": (None, [_P]),
+    "hx_pipeline_sync": (ctypes.c_int, [_P]),
+    "hx_pipeline_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(Schedule)]),
+    "hx_pipeline_get_schedule": (ctypes.c_int, [_P, _i64, _i64,
+                                                ctypes.POINTER(Schedule)]),
+    "hx_edge_detect": (ctypes.c_int, [_P, ctypes.POINTER(Image), _P, _P]),
+    "hx_edge_detect_batched": (ctypes.c_int, [_P, ctypes.POINTER(Image), _i32,
+                                              _P, _P]),
+    "hx_edge_detect_stages": (ctypes.c_int, [_P, ctypes.POINTER(Image), _P, _P,
+                                             _P, _P, _P, _P]),
+    "hx_autotune": (ctypes.c_int, [_P, _i64, _i64, ctypes.c_char_p]),
+    "hx_autotune_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "hx_serve_create": (ctypes.c_int, [_P, ctypes.POINTER(ServeParams), _P,
+                                       ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "hx_serve_submit": (ctypes.c_int, [_P, _P, _i64, _i64, _i64, ctypes.c_double,
+                                       ctypes.POINTER(_u64)]),
+    "hx_serve_poll": (ctypes.c_int, [_P, _u64, _P, _i64,
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "hx_serve_now": (ctypes.c_double, [_P]),
+    "hx_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                                      ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "hx_serve_destroy": (ctypes.c_int, [_P]),
+    "hx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "hx_last_error": (ctypes.c_char_p, []),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2503_10855_amd/build.py")
+_lib = ctypes.CDLL(LIB_PATH)
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class HxError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.hx_last_error().decode(errors="replace")
+        name = _lib.hx_status_str(status).decode()
+        super().__init__(f"{where}: {name}: {msg}")
+
+
+def _check(st, where):
+    if st != HX_OK:
+        raise HxError(st, where)
+
+
+def raw():
+    """The loaded ctypes library (for ABI-level tests)."""
+    return _lib
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def image_desc(src: torch.Tensor, mask: torch.Tensor) -> Image:
+    if src.dtype != torch.float32 or src.dim() != 2 or src.stride(1) != 1:
+        raise TypeError("src must be a 2-D float32 tensor with unit column stride")
+    if mask.dtype != torch.uint8 or mask.dim() != 2 or mask.stride(1) != 1:
+        raise TypeError("mask must be a 2-D uint8 tensor with unit column stride")
+    if tuple(mask.shape) != tuple(src.shape):
+        raise ValueError("mask and src shapes differ")
+    if not (src.is_cuda and mask.is_cuda):
+        raise ValueError("src and mask must be device tensors")
+    H, W = src.shape
+    return Image(src.data_ptr(), H, W, src.stride(0), mask.data_ptr(), mask.stride(0))
+
+
+class Pipeline:
+    """An hx_pipeline: constants, dynamic-constant sizes and scratch."""
+
+    def __init__(self, ksize=5, sigma=1.0, theta=0.1, max_pixels=1 << 25,
+                 max_images=1024, device=0, tile_w=0, tile_h=0, fusion_depth=0,
+                 pass_mode=0):
+        self.params = Params(ksize, sigma, theta, tile_w, tile_h, fusion_depth,
+                             pass_mode, max_pixels, max_images)
+        self.device = device
+        h = _P()
+        _check(_lib.hx_pipeline_create(ctypes.byref(self.params), device,
+                                       ctypes.byref(h)), "hx_pipeline_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hx_pipeline_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedule(self, tile_w=None, tile_h=None, fusion_depth=None,
+                     pass_mode=PASS_STORE, reduce_mode=REDUCE_TREE):
+        """Force a schedule; with no arguments restore automatic choice."""
+        if tile_w is None:
+            _check(_lib.hx_pipeline_set_schedule(self._h, None), "set_schedule")
+            return
+        s = Schedule(tile_w, tile_h, fusion_depth, pass_mode, reduce_mode)
+        _check(_lib.hx_pipeline_set_schedule(self._h, ctypes.byref(s)),
+               "set_schedule")
+
+    def schedule(self, H, W):
+        s = Schedule()
+        _check(_lib.hx_pipeline_get_schedule(self._h, H, W, ctypes.byref(s)),
+               "get_schedule")
+        return s.astuple()
+
+    def sync(self):
+        _check(_lib.hx_pipeline_sync(self._h), "hx_pipeline_sync")
+
+    def edge_detect(self, src, mask=None, dmax=None, stream=None):
+        if mask is None:
+            mask = torch.empty(src.shape, dtype=torch.uint8, device=src.device)
+        d = image_desc(src, mask)
+        _check(_lib.hx_edge_detect(self._h, ctypes.byref(d),
+                                   dmax.data_ptr() if dmax is not None else None,
+                                   _stream(stream)), "hx_edge_detect")
+        return mask
+
+    def edge_detect_batched(self, srcs, masks=None, dmax=None, stream=None):
+        if masks is None:
+            masks = [torch.empty(s.shape, dtype=torch.uint8, device=s.device)
+                     for s in srcs]
+        n = len(srcs)
+        arr = (Image * n)(*[image_desc(s, m) for s, m in zip(srcs, masks)])
+        _check(_lib.hx_edge_detect_batched(
+            self._h, arr, n, dmax.data_ptr() if dmax is not None else None,
+            _stream(stream)), "hx_edge_detect_batched")
+        return masks
+
+    def edge_detect_stages(self, src, stream=None):
+        H, W = src.shape
+        dev = src.device
+        out = dict(B=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   L=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   Z=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                   G=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   M=torch.empty(1, dtype=torch.float32, device=dev),
+                   mask=torch.empty((H, W), dtype=torch.uint8, device=dev))
+        d = image_desc(src, out["mask"])
+        _check(_lib.hx_edge_detect_stages(
+            self._h, ctypes.byref(d), out["B"].data_ptr(), out["L"].data_ptr(),
+            out["Z"].data_ptr(), out["G"].data_ptr(), out["M"].data_ptr(),
+            _stream(stream)), "hx_edge_detect_stages")
+        return out
+
+    def autotune(self, H, W, cache_path=None):
+        _check(_lib.hx_autotune(self._h, H, W,
+                                cache_path.encode() if cache_path else None),
+               "hx_autotune")
+        return self.schedule(H, W)
+
+    def autotune_load(self, cache_path):
+        _check(_lib.hx_autotune_load(self._h, cache_path.encode()),
+               "hx_autotune_load")
+
+
+class Server:
+    """An hx_server: continuous-batching request loop over a device arena."""
+
+    def __init__(self, pipeline: Pipeline, hbm_budget, streams=4, max_batch=64,
+                 arena: torch.Tensor = None):
+        if arena is None:
+            arena = torch.empty(hbm_budget, dtype=torch.uint8,
+                                device=f"cuda:{pipeline.device}")
+        self.arena = arena
+        self.pipeline = pipeline
+        self.sp = ServeParams(hbm_budget, streams, max_batch)
+        h = _P()
+        _check(_lib.hx_serve_create(pipeline.handle, ctypes.byref(self.sp),
+                                    arena.data_ptr(), arena.numel(),
+                                    ctypes.byref(h)), "hx_serve_create")
+        self._h = h
+
+    def now(self):
+        return _lib.hx_serve_now(self._h)
+
+    def submit(self, img, arrival=None):
+        """img: host float32 numpy array (H, W).  Returns a ticket."""
+        import numpy as np
+        a = np.ascontiguousarray(img, dtype=np.float32)
+        t = _u64()
+        _check(_lib.hx_serve_submit(self._h, a.ctypes.data, a.shape[0], a.shape[1],
+                                    a.shape[1], self.now() if arrival is None else arrival,
+                                    ctypes.byref(t)), "hx_serve_submit")
+        return t.value
+
+    def poll(self, ticket, shape):
+        """Returns (mask, latency_s) when done, or None while pending."""
+        import numpy as np
+        m = np.empty(shape, dtype=np.uint8)
+        lat = ctypes.c_double()
+        st = _lib.hx_serve_poll(self._h, ticket, m.ctypes.data, shape[1],
+                                ctypes.byref(lat))
+        if st == HX_E_PENDING:
+            return None
+        _check(st, "hx_serve_poll")
+        return m, lat.value
+
+    def stats(self):
+        v = [_u64() for _ in range(4)]
+        _check(_lib.hx_serve_stats(self._h, *[ctypes.byref(x) for x in v]),
+               "hx_serve_stats")
+        return dict(completed=v[0].value, batches=v[1].value, pixels=v[2].value,
+                    peak_bytes=v[3].value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.hx_serve_destroy(self._h), "hx_serve_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

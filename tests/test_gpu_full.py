@@ -1,0 +1,101 @@
+"""Parity at the full benchmark workload sizes, in the launch configuration
+the benchmark times (the batched persistent launch with the default
+schedule), against the oracle on every image."""
+import concurrent.futures as cf
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2503_10855_amd import synth
+
+pytestmark = pytest.mark.gpu
+THETA = 0.1
+
+
+@pytest.fixture(scope="module")
+def hx():
+    from paper_2503_10855_amd import hx as mod
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_all(imgs, ks, sigma):
+    n = min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(n) as ex:
+        return list(ex.map(lambda a: oracle.edge_detect(a, ks, sigma, THETA, stages=True),
+                           imgs))
+
+
+def check(masks, Ms, imgs, ks, sigma, what):
+    outs = oracle_all(imgs, ks, sigma)
+    tot = dict(mismatch=0, band=0, amb=0, exempt_diff=0)
+    for i, (m, M, o) in enumerate(zip(masks, Ms, outs)):
+        assert abs(M - o["M"]) <= 1e-5 * o["M"], (what, i, M, o["M"])
+        r = parity.compare_mask(m, o, THETA)
+        for k in tot:
+            tot[k] += r[k]
+        assert r["mismatch"] == 0, (what, i, r)
+    say(f"{what}: {len(imgs)} images, {tot}")
+
+
+def run_batched(p, imgs):
+    srcs = [torch.from_numpy(a).cuda() for a in imgs]
+    dmax = torch.zeros(len(imgs), device="cuda")
+    masks = p.edge_detect_batched(srcs, dmax=dmax)
+    p.sync()
+    return [m.cpu().numpy() for m in masks], dmax.cpu().numpy().tolist()
+
+
+def test_full_batch_64x1080p(hx):
+    wl = synth.batch_1080p()
+    imgs = [wl.image(i) for i in range(len(wl.sizes))]
+    say("batched 64x1920x1080 k5: launching")
+    with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=THETA,
+                     max_pixels=wl.pixels, max_images=len(imgs)) as p:
+        masks, Ms = run_batched(p, imgs)
+        say("per-image plain (depth 1) on 4 images: launching")
+        p.set_schedule(64, 16, 1)
+        plain = []
+        for a in imgs[:4]:
+            plain.append(p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy())
+    for i in range(4):
+        assert np.array_equal(plain[i], masks[i]), i
+    check(masks, Ms, imgs, wl.ksize, wl.sigma, "64x1080p batched")
+
+
+def test_full_8192_k7(hx):
+    wl = synth.large_8192()
+    img = wl.image(0)
+    say("8192x8192 k7 per-image and batched: launching")
+    with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=THETA,
+                     max_pixels=wl.pixels, max_images=4) as p:
+        src = torch.from_numpy(img).cuda()
+        dmax = torch.zeros(1, device="cuda")
+        m1 = p.edge_detect(src, dmax=dmax).cpu().numpy()
+        M1 = float(dmax.cpu()[0])
+        mb, Mb = run_batched(p, [img])
+    assert np.array_equal(m1, mb[0]) and M1 == Mb[0]
+    check([m1], [M1], [img], wl.ksize, wl.sigma, "8192^2 k7")
+
+
+def test_full_uneven_512(hx):
+    wl = synth.uneven_512()
+    say(f"uneven 512 images, {wl.pixels} pixels: generating")
+    imgs = [wl.image(i) for i in range(len(wl.sizes))]
+    say("uneven 512 batched: launching")
+    with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=THETA,
+                     max_pixels=wl.pixels, max_images=len(imgs)) as p:
+        masks, Ms = run_batched(p, imgs)
+        p.set_schedule(256, 64, 4, 2)
+        masks2, Ms2 = run_batched(p, imgs)
+    for a, b in zip(masks, masks2):
+        assert np.array_equal(a, b)
+    assert Ms == Ms2
+    check(masks, Ms, imgs, wl.ksize, wl.sigma, "uneven 512 batched")
