@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the EDGE pipeline on one MI355X.
+
+One step = the whole hot path (blur, Laplacian, zero crossing, Sobel, max
+reduction, threshold) over one batch of seeded synthetic images already
+resident in HBM.  The default workload is 64 images of 1920x1080 (5x5
+Gaussian, sigma 1), run as one batched graph launch; the same images are
+also timed through the per-image forms (fused and one kernel per stage)
+for the batched-vs-per-image comparison.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("Mpixel/s and %HBM-roofline, batched vs per-image; "
+          "p50/p99 latency at QPS")
+HBM_PEAK_GBS = 8000.0
+PASS1_BYTES_PER_PX = 4.0   # input read once (algorithmic)
+PATH_BYTES_PER_PX = 5.0    # input read once + mask written once
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_pass1.json")
+SWEEP_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in
+                 ("sweep_impl.h", "hx_device.h", "k_batch.hip", "thresh_impl.h")]
+
+
+def workloads():
+    from paper_2503_10855_amd import synth
+    return {"batch-64x1080p": synth.batch_1080p, "uneven-512": synth.uneven_512,
+            "single-8192-k7": synth.large_8192, "single-256": synth.single_256}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pixels):
+    """HBM bytes per pass-1 launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash() or t.get("pixels") != pixels:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, images, budget_s=20.0):
+    """The oracle (plain fp64 C) on a bounded sample of the workload."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.edge_detect(images[0], wl.ksize, wl.sigma, wl.theta)
+    one = time.perf_counter() - t0
+    n = int(max(1, min(len(images), budget_s / max(one, 1e-6))))
+    sample = images[:n]
+    t0 = time.perf_counter()
+    oracle.edge_detect_many(sample, wl.ksize, wl.sigma, wl.theta, nthreads=threads)
+    dt = time.perf_counter() - t0
+    px = sum(a.shape[0] * a.shape[1] for a in sample)
+    return {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": min(threads, n),
+            "kind": "oracle",
+            "sample": f"{n} of {len(images)} images of the workload, one image per "
+                      f"thread, fp64 C oracle, {dt:.2f} s wall"}
+
+
+def timed(fn, steps, warmup, sync):
+    import torch
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    sync()
+    wall = time.perf_counter() - w0
+    return t0.elapsed_time(t1) / steps, wall
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch-64x1080p", choices=sorted(workloads()))
+    ap.add_argument("--pass-mode", type=int, default=0, choices=(0, 1, 2))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-per-image", action="store_true",
+                    help="skip the per-image comparison forms")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device-to-device copy of MIB MiB, three "
+                         "times (calibrates the HBM byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); "
+              "images are independent, so several GPUs would each run their own "
+              "batches with no communication", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2503_10855_amd.build import LIB
+    if not os.path.exists(LIB):
+        from paper_2503_10855_amd.build import build
+        build()
+    from paper_2503_10855_amd import hx
+
+    wl = workloads()[args.workload]()
+    images = [wl.image(i) for i in range(len(wl.sizes))]
+    srcs = [torch.from_numpy(a).cuda() for a in images]
+    masks = [torch.empty(s.shape, dtype=torch.uint8, device="cuda") for s in srcs]
+    dmax = torch.zeros(len(srcs), device="cuda")
+    pixels = wl.pixels
+    sync = torch.cuda.synchronize
+
+    with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=wl.theta,
+                     max_pixels=pixels, max_images=max(len(srcs), 1),
+                     pass_mode=args.pass_mode) as p:
+        sched = p.schedule(*wl.sizes[0])
+
+        prepared = p.prepare_batch(srcs, masks, dmax)
+        batched = prepared.run
+
+        ms_step, wall = timed(batched, args.steps, args.warmup, sync)
+        p.sync()
+        value = pixels / (ms_step * 1e-3) / 1e6
+
+        # The same kernels launched directly with events around each one
+        # (timing mode): durations of pass 1, the dominant kernel.
+        p.set_timing(True)
+        for _ in range(args.warmup):
+            batched()
+        p.last_timing()
+        acc = np.zeros(3)
+        for _ in range(args.steps):
+            batched()
+            acc += np.array(p.last_timing())
+        p.set_timing(False)
+        ms_reset, ms_p1, ms_p2 = (acc / args.steps).tolist()
+
+        per_image = None
+        if not args.no_per_image:
+            ref = [m.clone() for m in masks]
+
+            def fused():
+                for s, m in zip(srcs, masks):
+                    p.edge_detect(s, m)
+            ms_fused, _ = timed(fused, max(1, args.steps // 2), 1, sync)
+            same = all(torch.equal(a, b) for a, b in zip(ref, masks))
+            p.set_schedule(64, 16, 1)
+            ms_plain, _ = timed(fused, max(1, args.steps // 4), 1, sync)
+            p.set_schedule()
+            per_image = {
+                "fused_mpx_s": round(pixels / (ms_fused * 1e-3) / 1e6, 1),
+                "plain_mpx_s": round(pixels / (ms_plain * 1e-3) / 1e6, 1),
+                "fused_ms_per_step": round(ms_fused, 4),
+                "plain_ms_per_step": round(ms_plain, 4),
+                "batched_over_plain": round(ms_plain / ms_step, 2),
+                "batched_over_fused": round(ms_fused / ms_step, 2),
+                "masks_identical_to_batched": bool(same),
+            }
+
+    achieved = PASS1_BYTES_PER_PX * pixels / (ms_p1 * 1e-3) / 1e9
+    traffic = measured_traffic(pixels)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "images": len(wl.sizes), "pixels": pixels,
+                   "ksize": wl.ksize, "sigma": wl.sigma, "theta": wl.theta,
+                   "form": "batched graph launch", "schedule": list(sched)},
+        "roofline": {"kernel": "pass 1 (fused sweep, k_batch_p1)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "ms_per_launch": round(ms_p1, 4),
+                     "bytes_per_px": PASS1_BYTES_PER_PX},
+        "path_roofline": {"achieved": round(PATH_BYTES_PER_PX * pixels / (ms_step * 1e-3) / 1e9, 1),
+                          "unit": "GB/s", "bytes_per_px": PATH_BYTES_PER_PX,
+                          "frac": round(PATH_BYTES_PER_PX * pixels / (ms_step * 1e-3)
+                                        / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms": {"reset": round(ms_reset, 4), "pass1": round(ms_p1, 4),
+                       "pass2": round(ms_p2, 4)},
+        "per_image": per_image,
+        "wall_s": round(wall, 3),
+    }
+    if args.calib_copy:
+        nbytes = args.calib_copy << 20
+        a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        sync()
+        for _ in range(3):
+            b.copy_(a)
+        sync()
+        line["calib_copy_bytes"] = nbytes
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, images)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,6 +140,15 @@ void hx_pipeline_destroy(hx_pipeline* p);
  * error. */
 hx_status hx_pipeline_sync(hx_pipeline* p);
 
+/* Timing mode, for benchmarks.  While enabled, batched calls launch their
+ * three kernels (reset, pass 1, pass 2) directly instead of through the
+ * graph and bracket each with HIP events on the call's stream.
+ * hx_pipeline_last_timing waits for the last batched call and returns the
+ * three durations in milliseconds (ms[0] reset, ms[1] pass 1, ms[2]
+ * pass 2).  HX_E_INVALID if no batched call ran in timing mode. */
+hx_status hx_pipeline_set_timing(hx_pipeline* p, int enable);
+hx_status hx_pipeline_last_timing(hx_pipeline* p, float* ms);
+
 /* Force a schedule for every later call (NULL restores automatic choice).
  * HX_E_INVALID for knob values outside the sets documented above,
  * HX_E_UNSUPPORTED for a fused depth with ksize not in {3,5,7}. */

@@ -232,6 +232,7 @@ static hx_status ctx_init(hx_pipeline* p, BatchContext& c) {
     if (c.ready) return HX_OK;
     HX_TRY(hipMalloc(&c.slots, sizeof(uint32_t) * p->prm.max_images));
     HX_TRY(hipEventCreateWithFlags(&c.ev_done, hipEventDisableTiming));
+    for (auto& e : c.ev_t) HX_TRY(hipEventCreate(&e));
     c.ready = true;
     return HX_OK;
 }
@@ -246,6 +247,8 @@ static void ctx_release(BatchContext& c) {
     if (c.h_table) (void)hipHostFree(c.h_table);
     if (c.slots) (void)hipFree(c.slots);
     if (c.ev_done) (void)hipEventDestroy(c.ev_done);
+    for (auto& e : c.ev_t)
+        if (e) (void)hipEventDestroy(e);
     c = BatchContext{};
 }
 
@@ -256,15 +259,21 @@ hx_status ctx_wait(BatchContext& c) {
     return HX_OK;
 }
 
-// Enqueue [reset, pass 1, pass 2] for this context on stream s.
-static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipStream_t s) {
-    hipError_t e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
+// Enqueue [reset, pass 1, pass 2] for this context on stream s; with
+// `timed`, bracket each launch with the context's timing events.
+static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipStream_t s,
+                                 bool timed = false) {
+    hipError_t e = timed ? hipEventRecord(c.ev_t[0], s) : hipSuccess;
+    if (e == hipSuccess) e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
+    if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[1], s);
     if (e == hipSuccess)
         e = launch_batch_phase(p->prm.ksize, pass, 1, c.table.ptr, p->taps,
                                p->batch_grid[pass][0], s);
+    if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[2], s);
     if (e == hipSuccess)
         e = launch_batch_phase(p->prm.ksize, pass, 2, c.table.ptr, p->taps,
                                p->batch_grid[pass][1], s);
+    if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[3], s);
     return e;
 }
 
@@ -299,6 +308,10 @@ static hx_status ctx_graph(hx_pipeline* p, BatchContext& c, int pass) {
     return HX_OK;
 }
 
+static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* imgs,
+                             int32_t n, float* d_max, int pass, const SweepGeom& geo,
+                             hipStream_t stream);
+
 hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
                       float* d_max, int pass, hipStream_t stream) {
     const int ks = p->prm.ksize;
@@ -317,6 +330,35 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
     st = ctx_wait(c);
     if (st != HX_OK) return st;
 
+    const bool same = c.last_pass == pass && c.last_dmax == d_max &&
+                      c.last_imgs.size() == (size_t)n &&
+                      std::memcmp(c.last_imgs.data(), imgs, sizeof(hx_image) * n) == 0;
+    if (!same) {
+        st = build_table(p, c, imgs, n, d_max, pass, geo, stream);
+        if (st != HX_OK) return st;
+    }
+    static const bool no_graph = std::getenv("HX_NO_GRAPH") != nullptr;
+    if (p->timing) {
+        HX_TRY(enqueue_phases(p, c, pass, stream, true));
+        p->last_timed_ctx = (int)(&c - p->ctx);
+    } else if (no_graph) {
+        HX_TRY(enqueue_phases(p, c, pass, stream));
+    } else {
+        st = ctx_graph(p, c, pass);
+        if (st != HX_OK) return st;
+        HX_TRY(hipGraphLaunch(c.exec[pass], stream));
+    }
+    HX_TRY(hipEventRecord(c.ev_done, stream));
+    c.in_flight = true;
+    return HX_OK;
+}
+
+// Build the descriptor table of a batch in the context's pinned staging
+// buffer and copy it to the device on `stream`.
+static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* imgs,
+                             int32_t n, float* d_max, int pass, const SweepGeom& geo,
+                             hipStream_t stream) {
+    c.last_pass = -1;  // the device table is stale until the copy is queued
     // Item counts and pass-1 store offsets.
     std::vector<int64_t> tiles(n), p2n(n), off(n);
     int64_t n1 = 0, n2 = 0, code_elems = 0;
@@ -363,16 +405,9 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
         for (int64_t t = 0; t < p2n[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
 
     HX_TRY(hipMemcpyAsync(c.table.ptr, h, bytes, hipMemcpyHostToDevice, stream));
-    static const bool no_graph = std::getenv("HX_NO_GRAPH") != nullptr;
-    if (no_graph) {
-        HX_TRY(enqueue_phases(p, c, pass, stream));
-    } else {
-        st = ctx_graph(p, c, pass);
-        if (st != HX_OK) return st;
-        HX_TRY(hipGraphLaunch(c.exec[pass], stream));
-    }
-    HX_TRY(hipEventRecord(c.ev_done, stream));
-    c.in_flight = true;
+    c.last_imgs.assign(imgs, imgs + n);
+    c.last_dmax = d_max;
+    c.last_pass = pass;
     return HX_OK;
 }
 
@@ -494,6 +529,25 @@ hx_status hx_pipeline_sync(hx_pipeline* p) {
     hipError_t e = hipDeviceSynchronize();
     if (first == HX_OK && e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     return first;
+}
+
+hx_status hx_pipeline_set_timing(hx_pipeline* p, int enable) {
+    if (!p) return fail(HX_E_INVALID, "pipeline is NULL");
+    std::lock_guard<std::mutex> lk(p->batch_mu);
+    p->timing = enable != 0;
+    if (!p->timing) p->last_timed_ctx = -1;
+    return HX_OK;
+}
+
+hx_status hx_pipeline_last_timing(hx_pipeline* p, float* ms) {
+    if (!p || !ms) return fail(HX_E_INVALID, "NULL argument");
+    DeviceGuard g(p->device);
+    std::lock_guard<std::mutex> lk(p->batch_mu);
+    if (p->last_timed_ctx < 0) return fail(HX_E_INVALID, "no batched call ran in timing mode");
+    BatchContext& c = p->ctx[p->last_timed_ctx];
+    HX_TRY(hipEventSynchronize(c.ev_t[3]));
+    for (int i = 0; i < 3; ++i) HX_TRY(hipEventElapsedTime(&ms[i], c.ev_t[i], c.ev_t[i + 1]));
+    return HX_OK;
 }
 
 hx_status hx_pipeline_set_schedule(hx_pipeline* p, const hx_schedule* s) {

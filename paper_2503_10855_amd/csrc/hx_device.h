@@ -84,31 +84,18 @@ __device__ __forceinline__ void atomic_max_g2(uint32_t* slot, float g2) {
     atomicMax(slot, __float_as_uint(g2));
 }
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) {
-    return v < lo ? lo : (v > hi ? hi : v);
+// Pointers read from a descriptor table are generic to the compiler;
+// casting them to the global address space lets it emit global (not flat)
+// loads and stores with a scalar base address.
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+    return (gptr<T>)p;
 }
 
-// ---- wave64 cross-lane moves (DPP; one VALU op each) -------------------
-// from_left: lane i receives lane i-1's value (lane 0 receives 0).
-// from_right: lane i receives lane i+1's value (lane 63 receives 0).
-__device__ __forceinline__ float from_left(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(
-        0, __float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float from_right(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(
-        0, __float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
-}
-template <int Q>
-__device__ __forceinline__ float lane_fetch(float v) {
-    // Value held by lane (self + Q).
-    if constexpr (Q == 0) {
-        return v;
-    } else if constexpr (Q > 0) {
-        return lane_fetch<Q - 1>(from_right(v));
-    } else {
-        return lane_fetch<Q + 1>(from_left(v));
-    }
+__device__ __forceinline__ int clampi(int v, int lo, int hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
 }
 
 // Max over the 64 lanes of a wave (xor butterfly); every lane gets it.

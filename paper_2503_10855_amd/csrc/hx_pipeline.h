@@ -52,12 +52,18 @@ struct BatchContext {
     uint32_t* slots = nullptr;  // max_images max slots
     DevBuf code;                // pass-1 store buffer
     hipEvent_t ev_done = nullptr;
+    hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};  // timing mode
     bool in_flight = false;
     // Captured [reset, pass 1, pass 2] per pass mode, with the table
     // address and grid sizes baked into the kernel nodes.
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
     const void* graph_table[3] = {nullptr, nullptr, nullptr};
+    // The call whose table the device copy holds: a repeat of the same
+    // batch (same descriptors, outputs and pass mode) reuses it as is.
+    std::vector<hx_image> last_imgs;
+    float* last_dmax = nullptr;
+    int last_pass = -1;
 };
 
 struct ShapeClass {
@@ -92,6 +98,8 @@ struct hx_pipeline {
                           // its own thread)
     hipStream_t capture_stream = nullptr;
     int batch_grid[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [pass mode][phase - 1]
+    bool timing = false;
+    int last_timed_ctx = -1;
 };
 
 namespace hx {

@@ -4,25 +4,32 @@
 // walks it downwards one input row per step.  Every stencil stage is a
 // fork over pixels (the paper's fork-join form); here they are fused into
 // one pass: each step
-//   A  loads input row v (prefetched PF rows ahead) and forms the
-//      horizontal blur Bh(v) of the lane's C columns (neighbour columns
-//      come from the adjacent lanes via DPP),
-//   B  finishes the vertical blur B(v-R) from the ring of the last k Bh
-//      rows, and its row pieces (e+w sums, Sobel dx and sy),
+//   A  takes input row v (loaded PF rows ahead) and forms the horizontal
+//      blur Bh(v) of the lane's C columns (neighbour columns come from the
+//      adjacent lanes via DPP moves),
+//   B  finishes the vertical blur B(v-R) from the last k Bh rows, and its
+//      row pieces (e+w sums, Sobel dx and sy),
 //   C  forms L and G^2 of row v-R-1 from the last three B rows, and the
 //      horizontal 3-max / 3-min of L,
 //   D  forms Z of row v-R-2 from three max/min rows and emits its output.
-// Rings are indexed by step mod P, and the step loop is unrolled by P, so
-// every ring slot is a fixed register.  Every value is computed by the
-// helpers in hx_device.h, in the same order as the depth-1 stage kernels.
+// The first 2R+4 steps fill this pipeline and are unrolled with
+// compile-time stage flags; the remaining TY steps run as a loop unrolled
+// by the ring period P = 8 (which divides TY), so every ring slot is a
+// fixed register and the steady state has no stage conditions.  Every
+// value is computed by the helpers in hx_device.h, in the same order as
+// the depth-1 stage kernels, so all schedules agree bit for bit.
 //
-// Borders: each stage reads its input at clamped coordinates.  Rows: the
-// input row index is clamped; a B or L row below the image is a copy of
-// the last real row; the row above the image is overwritten with row 0 as
-// soon as row 0 exists (before any valid output reads it).  Columns: the
-// input column is clamped, and the B and L values of columns outside the
-// image are replaced by the first / last real column's value.
+// Tiles whose whole input window lies inside the image (the common case)
+// run an instantiation with no border logic at all.  The others run one
+// that applies the clamped-coordinate rule per stage: rows -- the input
+// row index is clamped; a B or L row below the image is a copy of the last
+// real row; the row above the image is overwritten with row 0 as soon as
+// row 0 exists (before any valid output reads it); columns -- the input
+// column is clamped, and the B and L values of columns outside the image
+// are replaced by the first / last real column's value.
 #pragma once
+
+#include <utility>
 
 #include "hx_kernels.h"
 
@@ -35,13 +42,16 @@ struct SweepShape {
     static constexpr int HL = ((HX + C - 1) / C) * C;      // left halo
     static constexpr int SW = 64 * C;                      // strip width
     static constexpr int OW = ((SW - HL - HX) / C) * C;    // output width
-    static constexpr int P = KS >= 5 ? KS : 6;             // ring period
     static constexpr int NS = TY + 2 * HX;                 // steps
-    static constexpr int PF = P - 1 < 4 ? P - 1 : 4;       // prefetch rows
+    static constexpr int NP = 2 * R + 4;                   // pipeline fill
+    static constexpr int P = 8;                            // ring period
+    static constexpr int PF = 4;                           // prefetch rows
     static constexpr bool NEED_L =
         MODE == SM_STORE || MODE == SM_MASK || MODE == SM_BGL;
     static constexpr bool NEED_Z = MODE == SM_STORE || MODE == SM_MASK;
     static constexpr bool DO_MAX = MODE != SM_MASK;
+    static_assert(TY % P == 0, "tile height must be a multiple of the ring period");
+    static_assert(KS <= P, "the horizontal-blur ring must hold k rows");
 };
 
 template <int C>
@@ -49,15 +59,29 @@ struct alignas(4 * C) VecF {
     float v[C];
 };
 
-// Value of the lane (self + q), q a constant after unrolling.
-__device__ __forceinline__ float lane_fetch_q(float v, int q) {
-    if (q == 0) return v;
-    if (q == 1) return from_right(v);
-    if (q == -1) return from_left(v);
-    if (q == 2) return from_right(from_right(v));
-    if (q == -2) return from_left(from_left(v));
-    if (q == 3) return from_right(from_right(from_right(v)));
-    return from_left(from_left(from_left(v)));
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+template <class F, int... Is>
+__device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, Is...>) {
+    (f(IC<Is>{}), ...);
+}
+
+// Value held by lane (self + Q); lanes whose source is outside the wave
+// read 0 (those values only ever feed halo columns that are discarded).
+__device__ __forceinline__ float dpp_from_left(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float dpp_from_right(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
+}
+template <int Q>
+__device__ __forceinline__ float lane_fetch(float v) {
+    if constexpr (Q == 0) return v;
+    else if constexpr (Q > 0) return lane_fetch<Q - 1>(dpp_from_right(v));
+    else return lane_fetch<Q + 1>(dpp_from_left(v));
 }
 
 __device__ __forceinline__ float max3f(float a, float b, float c) {
@@ -98,24 +122,26 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 }
 
 // Run one tile: output columns [x0, x0+OW) x rows [y0, y0+TY), clipped to
-// the image.  thr2 is used by SM_MASK only.  gmax accumulates G^2 over the
-// tile's output pixels (per lane; the caller reduces it).
-template <int KS, int C, int TY, int MODE>
-__device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
+// the image.  BX / BY: the tile's input window crosses a column / row
+// border of the image.  thr2 is used by SM_MASK only.  gmax accumulates
+// G^2 over real image pixels of the tile (per lane; the caller reduces).
+template <int KS, int C, int TY, int MODE, bool BX, bool BY>
+__device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, float thr2,
                                            float& gmax) {
     using S = SweepShape<KS, C, TY, MODE>;
     constexpr int R = S::R, HX = S::HX, HL = S::HL, SW = S::SW, OW = S::OW;
-    constexpr int P = S::P, NS = S::NS, PF = S::PF;
+    constexpr int NS = S::NS, NP = S::NP, P = S::P, PF = S::PF;
 
     const int lane = lane_id();
     const int H = a.H, W = a.W;
     const int xs = x0 - HL;
     const int cbase = xs + C * lane;
-    const bool bx = (xs < 0) | (xs + SW > W);
-    const bool by = (y0 - HX < 0) | (y0 + TY + HX > H);
     const int ylim = min(y0 + TY, H);
     const bool lane_out = (cbase >= x0) & (cbase < x0 + OW);
+    // Lanes whose every column has a valid G^2 (its neighbourhood lies in
+    // the strip); outside the border variants those are all real pixels.
+    const bool gvalid = (cbase >= xs + R + 1) & (cbase + C <= xs + SW - R - 1);
     bool ecol[C];
 #pragma unroll
     for (int e = 0; e < C; ++e) ecol[e] = lane_out & (cbase + e < W);
@@ -125,26 +151,26 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
         ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
 
     auto load_row = [&](int v, float (&dst)[C]) {
-        const int row = by ? clampi(v, 0, H - 1) : v;
-        const float* rp = a.src + (int64_t)row * a.sp;
-        if (!bx & vec_ok) {
-            const VecF<C> q = *reinterpret_cast<const VecF<C>*>(rp + cbase);
+        const int row = BY ? clampi(v, 0, H - 1) : v;
+        const gptr<const float> rp = as_global(a.src) + (int64_t)row * a.sp;
+        if (!BX && vec_ok) {
+            const VecF<C> q = *(gptr<const VecF<C>>)(rp + cbase);
 #pragma unroll
             for (int e = 0; e < C; ++e) dst[e] = q.v[e];
         } else {
 #pragma unroll
             for (int e = 0; e < C; ++e)
-                dst[e] = rp[bx ? clampi(cbase + e, 0, W - 1) : cbase + e];
+                dst[e] = rp[BX ? clampi(cbase + e, 0, W - 1) : cbase + e];
         }
     };
     auto store_f = [&](float* base, int row, const float (&val)[C]) {
-        float* rp = base + (int64_t)row * a.op + cbase;
-        if (!bx) {
+        const gptr<float> rp = as_global(base) + (int64_t)row * a.op + cbase;
+        if constexpr (!BX) {
             if (lane_out) {
                 VecF<C> q;
 #pragma unroll
                 for (int e = 0; e < C; ++e) q.v[e] = val[e];
-                *reinterpret_cast<VecF<C>*>(rp) = q;
+                *(gptr<VecF<C>>)rp = q;
             }
         } else {
 #pragma unroll
@@ -162,175 +188,216 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
     float hmx[P][C];  // 3-wide max of L
     float hmn[P][C];  // 3-wide min of L
     float g2d[C];     // G^2 of the row waiting for its Z
+    float gacc = 0.0f;
 
-#pragma unroll
-    for (int j = 0; j < PF; ++j) load_row(y0 - HX + j, pf[j]);
+    // One step; J = s mod P, DB/DC/DD: stages B, C, D are active.
+    auto step = [&](auto jt, auto dbt, auto dct, auto ddt, int s) {
+        constexpr int J = decltype(jt)::value;
+        constexpr bool DB = decltype(dbt)::value != 0;
+        constexpr bool DC = decltype(dct)::value != 0;
+        constexpr bool DD = decltype(ddt)::value != 0;
+        constexpr int J1 = (J + P - 1) % P, J2 = (J + P - 2) % P;
+        const int v = y0 - HX + s;
+        if (s + PF < NS) load_row(v + PF, pf[(J + PF) % P]);
 
-    for (int s0 = 0; s0 < NS; s0 += P) {
+        // ---- A: horizontal blur of input row v
+        {
+            float ext[C + 2 * R];
+            static_for([&](auto kt) {
+                constexpr int kk = decltype(kt)::value - R;
+                constexpr int q = kk >= 0 ? kk / C : -((-kk + C - 1) / C);
+                ext[kk + R] = lane_fetch<q>(pf[J][kk - q * C]);
+            }, std::make_integer_sequence<int, C + 2 * R>{});
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int s = s0 + j;
-            if (s < NS) {
-                const int v = y0 - HX + s;
-                if (s + PF < NS) load_row(v + PF, pf[(j + PF) % P]);
+            for (int e = 0; e < C; ++e) bh[J][e] = blur_chain<KS>(&ext[e], tp);
+        }
 
-                // ---- A: horizontal blur of input row v
-                {
-                    float ext[C + 2 * R];
+        // ---- B: vertical blur, row vb = v - R
+        if constexpr (DB) {
+            const int vb = v - R;
+            float b[C];
 #pragma unroll
-                    for (int k = 0; k < C + 2 * R; ++k) {
-                        const int kk = k - R;
-                        const int q = kk >= 0 ? kk / C : -((-kk + C - 1) / C);
-                        ext[k] = lane_fetch_q(pf[j][kk - q * C], q);
-                    }
+            for (int e = 0; e < C; ++e) {
+                float col[KS];
 #pragma unroll
-                    for (int e = 0; e < C; ++e)
-                        bh[j][e] = blur_chain<KS>(&ext[e], tp);
+                for (int i = 0; i < KS; ++i) col[i] = bh[(J - 2 * R + i + 4 * P) % P][e];
+                b[e] = blur_chain<KS>(col, tp);
+            }
+            if constexpr (BY) {
+                if (vb >= H) {
+#pragma unroll
+                    for (int e = 0; e < C; ++e) b[e] = bb[J1][e];
                 }
-
-                // ---- B: vertical blur, row vb = v - R
-                if (s >= 2 * R) {
-                    const int vb = v - R;
-                    float b[C];
+            }
+            if constexpr (BX) fix_cols<C, HL, SW>(b, x0, xs, cbase, W);
+            const float bl0 = lane_fetch<-1>(b[C - 1]);
+            const float br0 = lane_fetch<1>(b[0]);
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                const float l = e > 0 ? b[e - 1] : bl0;
+                const float r = e < C - 1 ? b[e + 1] : br0;
+                bb[J][e] = b[e];
+                ew[J][e] = l + r;
+                dx[J][e] = sobel_dx(l, r);
+                sy[J][e] = sobel_sy(ew[J][e], b[e]);
+            }
+            if constexpr (BY) {
+                if (vb == 0) {  // the row above the image is row 0
 #pragma unroll
                     for (int e = 0; e < C; ++e) {
-                        float col[KS];
-#pragma unroll
-                        for (int i = 0; i < KS; ++i)
-                            col[i] = bh[(j - 2 * R + i + 4 * P) % P][e];
-                        b[e] = blur_chain<KS>(col, tp);
-                    }
-                    if (by && vb >= H) {
-#pragma unroll
-                        for (int e = 0; e < C; ++e) b[e] = bb[(j + P - 1) % P][e];
-                    }
-                    if (bx) fix_cols<C, HL, SW>(b, x0, xs, cbase, W);
-                    const float bl0 = from_left(b[C - 1]);
-                    const float br0 = from_right(b[0]);
-#pragma unroll
-                    for (int e = 0; e < C; ++e) {
-                        const float l = e > 0 ? b[e - 1] : bl0;
-                        const float r = e < C - 1 ? b[e + 1] : br0;
-                        bb[j][e] = b[e];
-                        ew[j][e] = l + r;
-                        dx[j][e] = sobel_dx(l, r);
-                        sy[j][e] = sobel_sy(ew[j][e], b[e]);
-                    }
-                    if (by && vb == 0) {
-#pragma unroll
-                        for (int e = 0; e < C; ++e) {
-                            bb[(j + P - 1) % P][e] = bb[j][e];
-                            dx[(j + P - 1) % P][e] = dx[j][e];
-                            sy[(j + P - 1) % P][e] = sy[j][e];
-                        }
-                    }
-                }
-
-                // ---- C: L and G^2 of row vl = v - R - 1
-                if (s >= 2 * R + 2) {
-                    const int vl = v - R - 1;
-                    const int ju = (j + 2 * P - 2) % P;
-                    const int jc = (j + P - 1) % P;
-                    float g2[C];
-#pragma unroll
-                    for (int e = 0; e < C; ++e)
-                        g2[e] = sobel_g2(dx[ju][e], dx[jc][e], dx[j][e], sy[ju][e],
-                                         sy[j][e]);
-                    const bool row_out = (vl >= y0) & (vl < ylim);
-                    if constexpr (S::DO_MAX) {
-                        if (row_out) {
-#pragma unroll
-                            for (int e = 0; e < C; ++e)
-                                gmax = __builtin_fmaxf(gmax, ecol[e] ? g2[e] : 0.0f);
-                        }
-                    }
-                    if constexpr (MODE == SM_BG) {
-                        if (row_out) {
-                            store_f(a.fout, vl, bb[jc]);
-                            store_f(a.g2, vl, g2);
-                        }
-                    }
-                    if constexpr (S::NEED_L) {
-                        float l[C];
-#pragma unroll
-                        for (int e = 0; e < C; ++e)
-                            l[e] = lap_from(bb[ju][e] + bb[j][e], ew[jc][e], bb[jc][e]);
-                        if constexpr (MODE == SM_BGL) {
-                            if (row_out) {
-                                store_f(a.fout, vl, l);
-                                store_f(a.g2, vl, g2);
-                            }
-                        }
-                        if constexpr (S::NEED_Z) {
-                            if (bx) fix_cols<C, HL, SW>(l, x0, xs, cbase, W);
-                            const float ll0 = from_left(l[C - 1]);
-                            const float lr0 = from_right(l[0]);
-#pragma unroll
-                            for (int e = 0; e < C; ++e) {
-                                const float lf = e > 0 ? l[e - 1] : ll0;
-                                const float rt = e < C - 1 ? l[e + 1] : lr0;
-                                hmx[j][e] = max3f(lf, l[e], rt);
-                                hmn[j][e] = min3f(lf, l[e], rt);
-                            }
-                            if (by && vl >= H) {
-#pragma unroll
-                                for (int e = 0; e < C; ++e) {
-                                    hmx[j][e] = hmx[jc][e];
-                                    hmn[j][e] = hmn[jc][e];
-                                }
-                            }
-                            if (by && vl == 0) {
-#pragma unroll
-                                for (int e = 0; e < C; ++e) {
-                                    hmx[jc][e] = hmx[j][e];
-                                    hmn[jc][e] = hmn[j][e];
-                                }
-                            }
-                            // ---- D: Z of row vz = vl - 1, and the output
-                            if (s >= 2 * R + 4) {
-                                const int vz = vl - 1;
-                                if ((vz >= y0) & (vz < ylim)) {
-                                    bool z[C];
-#pragma unroll
-                                    for (int e = 0; e < C; ++e)
-                                        z[e] = zero_cross(
-                                            max3f(hmx[ju][e], hmx[jc][e], hmx[j][e]),
-                                            min3f(hmn[ju][e], hmn[jc][e], hmn[j][e]));
-                                    if constexpr (MODE == SM_STORE) {
-                                        float code[C];
-#pragma unroll
-                                        for (int e = 0; e < C; ++e)
-                                            code[e] = pass1_code(z[e], g2d[e]);
-                                        store_f(a.fout, vz, code);
-                                    } else {
-                                        uint8_t* rp = a.mask + (int64_t)vz * a.mp + cbase;
-                                        uint32_t m[C];
-#pragma unroll
-                                        for (int e = 0; e < C; ++e)
-                                            m[e] = (z[e] & (g2d[e] > thr2)) ? 1u : 0u;
-                                        if (!bx & (C == 4) & mask_vec) {
-                                            if (lane_out) {
-                                                uint32_t w = 0;
-#pragma unroll
-                                                for (int e = 0; e < C; ++e) w |= m[e] << (8 * e);
-                                                *reinterpret_cast<uint32_t*>(rp) = w;
-                                            }
-                                        } else {
-#pragma unroll
-                                            for (int e = 0; e < C; ++e)
-                                                if (ecol[e]) rp[e] = (uint8_t)m[e];
-                                        }
-                                    }
-                                }
-                            }
-#pragma unroll
-                            for (int e = 0; e < C; ++e) g2d[e] = g2[e];
-                        }
+                        bb[J1][e] = bb[J][e];
+                        dx[J1][e] = dx[J][e];
+                        sy[J1][e] = sy[J][e];
                     }
                 }
             }
         }
+
+        // ---- C: L and G^2 of row vl = v - R - 1
+        if constexpr (DC) {
+            const int vl = v - R - 1;
+            float g2[C];
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                g2[e] = sobel_g2(dx[J2][e], dx[J1][e], dx[J][e], sy[J2][e], sy[J][e]);
+            if constexpr (S::DO_MAX) {
+                if constexpr (!BX && !BY) {
+                    // Every row of an interior tile is a real pixel row and
+                    // max is idempotent: no per-row masking needed.
+#pragma unroll
+                    for (int e = 0; e + 1 < C; e += 2) gacc = max3f(gacc, g2[e], g2[e + 1]);
+                    if constexpr (C % 2) gacc = __builtin_fmaxf(gacc, g2[C - 1]);
+                } else {
+                    if ((vl >= y0) & (vl < ylim)) {
+#pragma unroll
+                        for (int e = 0; e < C; ++e)
+                            gacc = __builtin_fmaxf(gacc, ecol[e] ? g2[e] : 0.0f);
+                    }
+                }
+            }
+            const bool row_out = (vl >= y0) & (vl < ylim);
+            if constexpr (MODE == SM_BG) {
+                if (row_out) {
+                    store_f(a.fout, vl, bb[J1]);
+                    store_f(a.g2, vl, g2);
+                }
+            }
+            if constexpr (S::NEED_L) {
+                float l[C];
+#pragma unroll
+                for (int e = 0; e < C; ++e)
+                    l[e] = lap_from(bb[J2][e] + bb[J][e], ew[J1][e], bb[J1][e]);
+                if constexpr (MODE == SM_BGL) {
+                    if (row_out) {
+                        store_f(a.fout, vl, l);
+                        store_f(a.g2, vl, g2);
+                    }
+                }
+                if constexpr (S::NEED_Z) {
+                    if constexpr (BX) fix_cols<C, HL, SW>(l, x0, xs, cbase, W);
+                    const float ll0 = lane_fetch<-1>(l[C - 1]);
+                    const float lr0 = lane_fetch<1>(l[0]);
+#pragma unroll
+                    for (int e = 0; e < C; ++e) {
+                        const float lf = e > 0 ? l[e - 1] : ll0;
+                        const float rt = e < C - 1 ? l[e + 1] : lr0;
+                        hmx[J][e] = max3f(lf, l[e], rt);
+                        hmn[J][e] = min3f(lf, l[e], rt);
+                    }
+                    if constexpr (BY) {
+                        if (vl >= H) {
+#pragma unroll
+                            for (int e = 0; e < C; ++e) {
+                                hmx[J][e] = hmx[J1][e];
+                                hmn[J][e] = hmn[J1][e];
+                            }
+                        }
+                        if (vl == 0) {
+#pragma unroll
+                            for (int e = 0; e < C; ++e) {
+                                hmx[J1][e] = hmx[J][e];
+                                hmn[J1][e] = hmn[J][e];
+                            }
+                        }
+                    }
+                    // ---- D: Z of row vz = vl - 1, and the output
+                    if constexpr (DD) {
+                        const int vz = vl - 1;
+                        if (!BY || ((vz >= y0) & (vz < ylim))) {
+                            bool z[C];
+#pragma unroll
+                            for (int e = 0; e < C; ++e)
+                                z[e] = zero_cross(max3f(hmx[J2][e], hmx[J1][e], hmx[J][e]),
+                                                  min3f(hmn[J2][e], hmn[J1][e], hmn[J][e]));
+                            if constexpr (MODE == SM_STORE) {
+                                float code[C];
+#pragma unroll
+                                for (int e = 0; e < C; ++e) code[e] = pass1_code(z[e], g2d[e]);
+                                store_f(a.fout, vz, code);
+                            } else {
+                                const gptr<uint8_t> rp =
+                                    as_global(a.mask) + (int64_t)vz * a.mp + cbase;
+                                uint32_t m[C];
+#pragma unroll
+                                for (int e = 0; e < C; ++e)
+                                    m[e] = (z[e] & (g2d[e] > thr2)) ? 1u : 0u;
+                                if (!BX && (C == 4) && mask_vec) {
+                                    if (lane_out) {
+                                        uint32_t w = 0;
+#pragma unroll
+                                        for (int e = 0; e < C; ++e) w |= m[e] << (8 * e);
+                                        *(gptr<uint32_t>)rp = w;
+                                    }
+                                } else {
+#pragma unroll
+                                    for (int e = 0; e < C; ++e)
+                                        if (ecol[e]) rp[e] = (uint8_t)m[e];
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < C; ++e) g2d[e] = g2[e];
+                }
+            }
+        }
+    };
+
+    // Prefetch, then the pipeline fill with compile-time stage flags.
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_row(y0 - HX + j, pf[j]);
+    static_for([&](auto st) {
+        constexpr int s = decltype(st)::value;
+        step(IC<s % P>{}, IC<(s >= 2 * R)>{}, IC<(s >= 2 * R + 2)>{},
+             IC<(s >= 2 * R + 4)>{}, s);
+    }, std::make_integer_sequence<int, NP>{});
+    // Steady state: every stage active, TY steps in groups of P.
+    for (int s0 = NP; s0 < NS; s0 += P) {
+        static_for([&](auto jt) {
+            constexpr int jj = decltype(jt)::value;
+            step(IC<(NP + jj) % P>{}, IC<1>{}, IC<1>{}, IC<1>{}, s0 + jj);
+        }, std::make_integer_sequence<int, P>{});
     }
+    if constexpr (!BX && !BY) gacc = gvalid ? gacc : 0.0f;
+    gmax = __builtin_fmaxf(gmax, gacc);
+}
+
+template <int KS, int C, int TY, int MODE>
+__device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
+                                           int x0, int y0, float thr2,
+                                           float& gmax) {
+    using S = SweepShape<KS, C, TY, MODE>;
+    const int xs = x0 - S::HL;
+    const bool bx = (xs < 0) | (xs + S::SW > a.W);
+    const bool by = (y0 - S::HX < 0) | (y0 + TY + S::HX > a.H);
+    if (!bx & !by)
+        sweep_body<KS, C, TY, MODE, false, false>(a, tp, x0, y0, thr2, gmax);
+    else if (!bx)
+        sweep_body<KS, C, TY, MODE, false, true>(a, tp, x0, y0, thr2, gmax);
+    else if (!by)
+        sweep_body<KS, C, TY, MODE, true, false>(a, tp, x0, y0, thr2, gmax);
+    else
+        sweep_body<KS, C, TY, MODE, true, true>(a, tp, x0, y0, thr2, gmax);
 }
 
 }  // namespace hx

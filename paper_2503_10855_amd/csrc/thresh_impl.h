@@ -10,11 +10,15 @@ namespace hx {
 // 4 floats, 16-byte aligned), so the float4 read stays inside the row.
 __device__ __forceinline__ void threshold4(const ImgArgs& a, int y, int x,
                                            float thr2, bool mvec) {
-    const float4 c = *reinterpret_cast<const float4*>(a.fout + (int64_t)y * a.op + x);
-    const uint32_t m0 = c.x > thr2, m1 = c.y > thr2, m2 = c.z > thr2, m3 = c.w > thr2;
-    uint8_t* rp = a.mask + (int64_t)y * a.mp + x;
+    struct alignas(16) F4 {
+        float v[4];
+    };
+    const F4 c = *(gptr<const F4>)(as_global(a.fout) + (int64_t)y * a.op + x);
+    const uint32_t m0 = c.v[0] > thr2, m1 = c.v[1] > thr2, m2 = c.v[2] > thr2,
+                   m3 = c.v[3] > thr2;
+    const gptr<uint8_t> rp = as_global(a.mask) + (int64_t)y * a.mp + x;
     if (mvec & (x + 3 < a.W)) {
-        *reinterpret_cast<uint32_t*>(rp) = m0 | (m1 << 8) | (m2 << 16) | (m3 << 24);
+        *(gptr<uint32_t>)rp = m0 | (m1 << 8) | (m2 << 16) | (m3 << 24);
     } else {
         const uint32_t mm[4] = {m0, m1, m2, m3};
         for (int e = 0; e < 4 && x + e < a.W; ++e) rp[e] = (uint8_t)mm[e];

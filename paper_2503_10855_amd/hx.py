@@ -60,6 +60,8 @@ _SIGS = {
     "hx_pipeline_destroy": (None, [_P]),
     "hx_pipeline_sync": (ctypes.c_int, [_P]),
     "hx_pipeline_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(Schedule)]),
+    "hx_pipeline_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "hx_pipeline_last_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
     "hx_pipeline_get_schedule": (ctypes.c_int, [_P, _i64, _i64,
                                                 ctypes.POINTER(Schedule)]),
     "hx_edge_detect": (ctypes.c_int, [_P, ctypes.POINTER(Image), _P, _P]),
@@ -183,6 +185,16 @@ class Pipeline:
     def sync(self):
         _check(_lib.hx_pipeline_sync(self._h), "hx_pipeline_sync")
 
+    def set_timing(self, enable=True):
+        _check(_lib.hx_pipeline_set_timing(self._h, 1 if enable else 0), "set_timing")
+
+    def last_timing(self):
+        """(reset, pass 1, pass 2) durations in ms of the last batched call
+        made in timing mode (waits for it)."""
+        ms = (ctypes.c_float * 3)()
+        _check(_lib.hx_pipeline_last_timing(self._h, ms), "last_timing")
+        return tuple(ms)
+
     def edge_detect(self, src, mask=None, dmax=None, stream=None):
         if mask is None:
             mask = torch.empty(src.shape, dtype=torch.uint8, device=src.device)
@@ -202,6 +214,11 @@ class Pipeline:
             self._h, arr, n, dmax.data_ptr() if dmax is not None else None,
             _stream(stream)), "hx_edge_detect_batched")
         return masks
+
+    def prepare_batch(self, srcs, masks=None, dmax=None):
+        """Marshal the descriptors of a batch once; the returned object's
+        run() makes the batched call without rebuilding them."""
+        return PreparedBatch(self, srcs, masks, dmax)
 
     def edge_detect_stages(self, src, stream=None):
         H, W = src.shape
@@ -228,6 +245,26 @@ class Pipeline:
     def autotune_load(self, cache_path):
         _check(_lib.hx_autotune_load(self._h, cache_path.encode()),
                "hx_autotune_load")
+
+
+class PreparedBatch:
+    """A batch whose C descriptors are built once (see Pipeline.prepare_batch).
+    The tensors are kept alive by this object."""
+
+    def __init__(self, pipeline, srcs, masks=None, dmax=None):
+        if masks is None:
+            masks = [torch.empty(s.shape, dtype=torch.uint8, device=s.device)
+                     for s in srcs]
+        self.pipeline, self.srcs, self.masks, self.dmax = pipeline, srcs, masks, dmax
+        self.n = len(srcs)
+        self.arr = (Image * self.n)(*[image_desc(s, m) for s, m in zip(srcs, masks)])
+        self.dmax_ptr = dmax.data_ptr() if dmax is not None else None
+
+    def run(self, stream=None):
+        _check(_lib.hx_edge_detect_batched(self.pipeline.handle, self.arr, self.n,
+                                           self.dmax_ptr, _stream(stream)),
+               "hx_edge_detect_batched")
+        return self.masks
 
 
 class Server:
