@@ -154,9 +154,9 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         const int row = BY ? clampi(v, 0, H - 1) : v;
         const gptr<const float> rp = as_global(a.src) + (int64_t)row * a.sp;
         if (!BX && vec_ok) {
-            const VecF<C> q = *(gptr<const VecF<C>>)(rp + cbase);
+            const gptr<const VecF<C>> q = (gptr<const VecF<C>>)(rp + cbase);
 #pragma unroll
-            for (int e = 0; e < C; ++e) dst[e] = q.v[e];
+            for (int e = 0; e < C; ++e) dst[e] = q->v[e];
         } else {
 #pragma unroll
             for (int e = 0; e < C; ++e)
@@ -167,10 +167,9 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         const gptr<float> rp = as_global(base) + (int64_t)row * a.op + cbase;
         if constexpr (!BX) {
             if (lane_out) {
-                VecF<C> q;
+                const gptr<VecF<C>> q = (gptr<VecF<C>>)rp;
 #pragma unroll
-                for (int e = 0; e < C; ++e) q.v[e] = val[e];
-                *(gptr<VecF<C>>)rp = q;
+                for (int e = 0; e < C; ++e) q->v[e] = val[e];
             }
         } else {
 #pragma unroll
