@@ -211,6 +211,13 @@ def main():
         "per_image": per_image,
         "wall_s": round(wall, 3),
     }
+    # A plain 1 GiB device-to-device copy: the practical HBM ceiling.
+    cb = 1 << 30
+    ca = torch.ones(cb, dtype=torch.uint8, device="cuda")
+    cbuf = torch.empty_like(ca)
+    ms_copy, _ = timed(lambda: cbuf.copy_(ca), 10, 2, sync)
+    line["copy_gbs"] = round(2 * cb / (ms_copy * 1e-3) / 1e9, 1)
+    del ca, cbuf
     if args.calib_copy:
         nbytes = args.calib_copy << 20
         a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")

@@ -1,0 +1,178 @@
+// hx_tune.cpp -- the autotuner: the role the paper gives its schedules
+// (fork tiling / chunking / reshaping, fusion, fission; Juno Scheduling
+// Language and Use and Impact of Schedules) played by a search over the
+// knobs this implementation exposes: tile shape x fusion depth x pass
+// structure.  Every candidate computes bit-identical results (the per-pixel
+// operation order is fixed), so the choice is purely a matter of speed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hx_kernels.h"
+#include "hx_pipeline.h"
+
+namespace hx {
+
+namespace {
+
+// A seeded test image: hashed noise in [0, 0.2) plus a grid of bright
+// rectangles, written on the device (timing does not depend on content:
+// the kernels have no data-dependent control flow).
+__global__ void k_tune_image(float* img, int64_t pitch, int H, int W) {
+    const int64_t n = (int64_t)H * W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+        uint32_t h = (uint32_t)i * 2654435761u ^ 0x9e3779b9u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        float v = (float)(h & 0xffffu) * (0.2f / 65536.0f);
+        if (((x / 97) + (y / 61)) % 5 == 0) v = 0.5f + 0.1f * (float)((x / 97) % 5);
+        img[(int64_t)y * pitch + x] = v;
+    }
+}
+
+std::vector<hx_schedule> candidates(int ks) {
+    std::vector<hx_schedule> c;
+    for (int tw : {16, 32, 64})
+        for (int th : {16, 32}) c.push_back({tw, th, 1, HX_PASS_STORE, HX_REDUCE_TREE});
+    if (ks == 3 || ks == 5 || ks == 7) {
+        for (int depth : {2, 3, 4})
+            for (int tw : {64, 128, 256})
+                for (int th : {16, 32, 64, 128}) {
+                    if (depth < 4) {
+                        c.push_back({tw, th, depth, HX_PASS_STORE, HX_REDUCE_TREE});
+                    } else {
+                        c.push_back({tw, th, 4, HX_PASS_STORE, HX_REDUCE_TREE});
+                        c.push_back({tw, th, 4, HX_PASS_RECOMPUTE, HX_REDUCE_TREE});
+                    }
+                }
+    }
+    return c;
+}
+
+// Minimal reader for the cache lines this file writes.
+bool parse_entry(const char* line, int* ks, int* hb, int* wb, hx_schedule* s) {
+    return std::sscanf(line,
+                       " {\"ksize\": %d, \"hb\": %d, \"wb\": %d, \"schedule\": [%d, %d, %d, %d, %d]",
+                       ks, hb, wb, &s->tile_w, &s->tile_h, &s->fusion_depth, &s->pass_mode,
+                       &s->reduce_mode) == 8;
+}
+
+}  // namespace
+
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" {
+
+hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char* cache_path) {
+    if (!p) return fail(HX_E_INVALID, "pipeline is NULL");
+    if (height < 1 || width < 1 || height * width > p->prm.max_pixels)
+        return fail(HX_E_INVALID, "tuning shape %lldx%lld invalid or above max_pixels",
+                    (long long)height, (long long)width);
+    DeviceGuard g(p->device);
+    const int64_t pitch = (width + 63) & ~int64_t(63);
+    float* img = nullptr;
+    uint8_t* mask = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&img, sizeof(float) * pitch * height);
+    if (e == hipSuccess) e = hipMalloc(&mask, (size_t)pitch * height);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto cleanup = [&]() {
+        if (img) (void)hipFree(img);
+        if (mask) (void)hipFree(mask);
+        if (s) (void)hipStreamDestroy(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "autotune allocation");
+    }
+    hipLaunchKernelGGL(k_tune_image, dim3(1024), dim3(256), 0, s, img, pitch, (int)height,
+                       (int)width);
+    hx_image im{img, height, width, pitch, mask, pitch};
+    hx_schedule best{};
+    float best_ms = 1e30f;
+    hx_status st = HX_OK;
+    const bool was_forced = p->forced;
+    p->forced = false;
+    for (const hx_schedule& c : candidates(p->prm.ksize)) {
+        if (validate_schedule(p, c) != HX_OK) continue;
+        // One warm-up call (allocates scratch), then the fastest of three.
+        st = run_image(p, &im, nullptr, c, s);
+        if (st != HX_OK) break;
+        float ms_min = 1e30f;
+        for (int r = 0; r < 3 && st == HX_OK; ++r) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) st = run_image(p, &im, nullptr, c, s);
+            if (e == hipSuccess && st == HX_OK) e = hipEventRecord(e1, s);
+            if (e == hipSuccess && st == HX_OK) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess && st == HX_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+            if (ms < ms_min) ms_min = ms;
+        }
+        if (st != HX_OK) break;
+        if (std::getenv("HX_TUNE_LOG"))
+            std::fprintf(stderr, "tune %lldx%lld k%d: %dx%d depth %d pass %d: %.4f ms\n",
+                         (long long)height, (long long)width, p->prm.ksize, c.tile_w, c.tile_h,
+                         c.fusion_depth, c.pass_mode, ms_min);
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = c;
+        }
+    }
+    p->forced = was_forced;
+    e = hipStreamSynchronize(s);
+    cleanup();
+    if (st != HX_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (best_ms >= 1e30f) return fail(HX_E_UNSUPPORTED, "no schedule could run");
+    const ShapeClass sc = shape_class(height, width);
+    p->tuned[sc] = best;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(HX_E_INVALID, "cannot open autotune cache %s", cache_path);
+        std::fprintf(f,
+                     "{\"ksize\": %d, \"hb\": %d, \"wb\": %d, \"schedule\": [%d, %d, %d, %d, %d], "
+                     "\"ms\": %.5f, \"height\": %lld, \"width\": %lld}\n",
+                     p->prm.ksize, sc.hb, sc.wb, best.tile_w, best.tile_h, best.fusion_depth,
+                     best.pass_mode, best.reduce_mode, best_ms, (long long)height,
+                     (long long)width);
+        std::fclose(f);
+    }
+    return HX_OK;
+}
+
+hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path) {
+    if (!p || !cache_path) return fail(HX_E_INVALID, "NULL argument");
+    FILE* f = std::fopen(cache_path, "r");
+    if (!f) return fail(HX_E_NOT_FOUND, "cannot open autotune cache %s", cache_path);
+    char line[512];
+    int loaded = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        int ks, hb, wb;
+        hx_schedule s{};
+        if (!parse_entry(line, &ks, &hb, &wb, &s) || ks != p->prm.ksize) continue;
+        if (validate_schedule(p, s) != HX_OK) continue;
+        p->tuned[ShapeClass{hb, wb}] = s;  // later lines win
+        ++loaded;
+    }
+    std::fclose(f);
+    if (!loaded) return fail(HX_E_NOT_FOUND, "no usable entries in %s", cache_path);
+    return HX_OK;
+}
+
+}  // extern "C"

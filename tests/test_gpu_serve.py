@@ -1,0 +1,89 @@
+"""The serving loop: continuous batching under an HBM budget.  Each
+request's mask must be the same served alone and served in a mix (bit for
+bit), match the per-image call, and match the oracle."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2503_10855_amd import synth
+
+pytestmark = pytest.mark.gpu
+THETA = 0.1
+
+
+@pytest.fixture(scope="module")
+def hx():
+    from paper_2503_10855_amd import hx as mod
+    return mod
+
+
+def collect(srv, tickets, shapes, timeout=60.0):
+    out = {}
+    t_end = time.time() + timeout
+    while len(out) < len(tickets):
+        assert time.time() < t_end, f"{len(tickets) - len(out)} requests never completed"
+        for t, sh in zip(tickets, shapes):
+            if t in out:
+                continue
+            r = srv.poll(t, sh)
+            if r is not None:
+                out[t] = r
+        time.sleep(0.001)
+    return [out[t] for t in tickets]
+
+
+def test_serve_alone_equals_in_mix(hx):
+    sizes = synth.log_uniform_sizes(48, 64, 1024, 77)
+    imgs = [synth.image(h, w, 78, i) for i, (h, w) in enumerate(sizes)]
+    picks = [0, 17, 40]
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 24, max_images=64) as p:
+        alone = {}
+        for i in picks:
+            with hx.Server(p, hbm_budget=256 << 20, streams=2, max_batch=16) as srv:
+                print(f"serve alone {i} {sizes[i]}", flush=True)
+                t = srv.submit(imgs[i])
+                alone[i] = collect(srv, [t], [sizes[i]])[0][0]
+        print("serve mix of 48", flush=True)
+        with hx.Server(p, hbm_budget=256 << 20, streams=3, max_batch=16) as srv:
+            tickets = []
+            for a in imgs:
+                tickets.append(srv.submit(a))
+                time.sleep(0.0005)  # arrivals spread over the run
+            res = collect(srv, tickets, sizes)
+            st = srv.stats()
+        print(f"stats {st}", flush=True)
+        assert st["completed"] == len(imgs) and st["batches"] >= 2
+        per_image = [p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
+    for i in picks:
+        assert np.array_equal(alone[i], res[i][0]), i
+    for i, ((m, lat), ref) in enumerate(zip(res, per_image)):
+        assert np.array_equal(m, ref), i
+        assert lat > 0
+    for i in range(0, len(imgs), 6):
+        o = oracle.edge_detect(imgs[i], 5, 1.0, THETA, stages=True)
+        r = parity.compare_mask(res[i][0], o, THETA)
+        assert r["mismatch"] == 0, (i, r)
+
+
+def test_serve_admission_respects_budget(hx):
+    budget = 3 << 20  # about two 512x512 requests at a time
+    sizes = [(512, 512)] * 12 + [(300, 700)] * 4
+    imgs = [synth.image(h, w, 79, i) for i, (h, w) in enumerate(sizes)]
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 22, max_images=16) as p:
+        with hx.Server(p, hbm_budget=budget, streams=2, max_batch=8) as srv:
+            print("serve under a 3 MiB budget", flush=True)
+            tickets = [srv.submit(a) for a in imgs]
+            res = collect(srv, tickets, sizes)
+            st = srv.stats()
+            with pytest.raises(hx.HxError) as ei:
+                srv.submit(np.zeros((2048, 2048), np.float32))
+            assert ei.value.status == hx.HX_E_BUSY
+        refs = [p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
+    print(f"stats {st}", flush=True)
+    assert st["peak_bytes"] <= budget and st["completed"] == len(imgs)
+    for (m, _), ref in zip(res, refs):
+        assert np.array_equal(m, ref)
