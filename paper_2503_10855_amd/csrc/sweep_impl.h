@@ -329,10 +329,23 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                 z[e] = zero_cross(max3f(hmx[J2][e], hmx[J1][e], hmx[J][e]),
                                                   min3f(hmn[J2][e], hmn[J1][e], hmn[J][e]));
                             if constexpr (MODE == SM_STORE) {
-                                float code[C];
+                                uint32_t code[C];
 #pragma unroll
-                                for (int e = 0; e < C; ++e) code[e] = pass1_code(z[e], g2d[e]);
-                                store_f(a.fout, vz, code);
+                                for (int e = 0; e < C; ++e) code[e] = pass1_code16(z[e], g2d[e]);
+                                const gptr<uint16_t> cp =
+                                    as_global(a.code) + (int64_t)vz * a.cp + cbase;
+                                if constexpr (!BX && C % 2 == 0) {
+                                    if (lane_out) {
+#pragma unroll
+                                        for (int e = 0; e < C; e += 2)
+                                            ((gptr<uint32_t>)cp)[e / 2] =
+                                                code[e] | (code[e + 1] << 16);
+                                    }
+                                } else {
+#pragma unroll
+                                    for (int e = 0; e < C; ++e)
+                                        if (ecol[e]) cp[e] = (uint16_t)code[e];
+                                }
                             } else {
                                 const gptr<uint8_t> rp =
                                     as_global(a.mask) + (int64_t)vz * a.mp + cbase;
