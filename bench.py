@@ -196,7 +196,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "images": len(wl.sizes), "pixels": pixels,
                    "ksize": wl.ksize, "sigma": wl.sigma, "theta": wl.theta,
-                   "form": "batched graph launch", "schedule": list(sched)},
+                   "form": "batched graph launch",
+                   "pass_mode": {0: "recompute (batch default)", 1: "store",
+                                 2: "recompute"}[args.pass_mode],
+                   "per_image_schedule": list(sched)},
         "roofline": {"kernel": "pass 1 (fused sweep, k_batch_p1)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -75,7 +75,6 @@ ShapeClass shape_class(int64_t H, int64_t W) {
 }
 
 static int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
-static int64_t round8(int64_t v) { return (v + 7) & ~int64_t(7); }
 
 static bool fused_ks(int ks) { return ks == 3 || ks == 5 || ks == 7; }
 
@@ -154,7 +153,6 @@ static ImgArgs base_args(const hx_image* img, uint32_t* slot, float* d_max) {
     a.H = (int32_t)img->height;
     a.W = (int32_t)img->width;
     a.op = round4(img->width);
-    a.cp = round8(img->width);
     return a;
 }
 
@@ -174,10 +172,10 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
     if (s.fusion_depth == 4) {
         const int c = s.tile_w / 64;
         if (s.pass_mode == HX_PASS_STORE) {
-            HX_TRY(p->code1.ensure((size_t)a.H * (size_t)a.cp * sizeof(uint16_t)));
-            a.code = (uint16_t*)p->code1.ptr;
+            HX_TRY(p->code1.ensure(plane * sizeof(float)));
+            a.fout = (float*)p->code1.ptr;
             HX_TRY(launch_sweep(SM_STORE, ks, c, s.tile_h, a, p->taps, theta, stream));
-            HX_TRY(launch_threshold_code(a, p->taps, ks, theta, p->exact_all, stream));
+            HX_TRY(launch_threshold_code(a, theta, stream));
         } else {
             HX_TRY(launch_sweep(SM_MAXONLY, ks, c, s.tile_h, a, p->taps, theta, stream));
             HX_TRY(launch_sweep(SM_MASK, ks, c, s.tile_h, a, p->taps, theta, stream));
@@ -371,11 +369,11 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
         n1 += tiles[i];
         n2 += p2n[i];
         off[i] = code_elems;
-        if (pass == HX_PASS_STORE) code_elems += imgs[i].height * round8(imgs[i].width);
+        if (pass == HX_PASS_STORE) code_elems += imgs[i].height * round4(imgs[i].width);
     }
     if (n1 >= (int64_t(1) << 31) || n2 >= (int64_t(1) << 31))
         return fail(HX_E_INVALID, "batch has too many work items");
-    if (pass == HX_PASS_STORE) HX_TRY(c.code.ensure((size_t)code_elems * sizeof(uint16_t)));
+    if (pass == HX_PASS_STORE) HX_TRY(c.code.ensure((size_t)code_elems * sizeof(float)));
     const size_t bytes = batch_table_bytes(n, n1, n2);
     HX_TRY(c.table.ensure(bytes));
     if (c.h_table_bytes < bytes) {
@@ -394,12 +392,11 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
     hdr.n_items2 = (int32_t)n2;
     hdr.pass_mode = pass;
     hdr.theta = p->prm.thresh_frac;
-    hdr.exact_all = p->exact_all;
     std::memcpy(h, &hdr, sizeof hdr);
     ImgArgs* ia = (ImgArgs*)(h + sizeof(BatchHeader));
     for (int i = 0; i < n; ++i) {
         ia[i] = base_args(&imgs[i], c.slots + i, d_max ? d_max + i : nullptr);
-        if (pass == HX_PASS_STORE) ia[i].code = (uint16_t*)c.code.ptr + off[i];
+        if (pass == HX_PASS_STORE) ia[i].fout = (float*)c.code.ptr + off[i];
     }
     BatchItem* it = (BatchItem*)(ia + n);
     for (int i = 0; i < n; ++i)
@@ -474,7 +471,6 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
     if (!p) return fail(HX_E_NOMEM, "host allocation failed");
     p->device = device;
     p->prm = prm;
-    p->exact_all = std::getenv("HX_EXACT_CODES") != nullptr;
     compute_taps(prm.ksize, prm.sigma, p->taps);
     hx_schedule probe{prm.tile_w, prm.tile_h, prm.fusion_depth, prm.pass_mode, HX_REDUCE_TREE};
     if (prm.fusion_depth || prm.tile_w || prm.tile_h || prm.pass_mode) {
@@ -615,7 +611,10 @@ hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs, int32_t n
         }
         return HX_OK;
     }
-    int pass = HX_PASS_STORE;
+    // Batches default to RECOMPUTE: two reads of the input but no code
+    // round trip, measured faster on the 64x1080p batch (both passes run
+    // near the copy bandwidth).
+    int pass = HX_PASS_RECOMPUTE;
     if (p->prm.pass_mode) pass = p->prm.pass_mode;
     if (p->forced && p->forced_sched.fusion_depth == 4) pass = p->forced_sched.pass_mode;
     return run_batched(p, imgs, n, d_max, pass, stream);

@@ -63,22 +63,9 @@ __device__ __forceinline__ bool zero_cross(float lmax, float lmin) {
     return (lmax > 0.0f) & !(lmin > 0.0f);
 }
 
-// Pass-1 store code, 16 bits per pixel: where Z = 1, the upper half of
-// G^2's IEEE bits (G^2 truncated to bfloat16, so the exact value lies in
-// [lo, next(lo))); where Z = 0, a code with the sign bit set.
-constexpr uint16_t kCodeNoEdge = 0x8000u;
-__device__ __forceinline__ uint16_t pass1_code16(bool z, float g2) {
-    return z ? (uint16_t)(__float_as_uint(g2) >> 16) : kCodeNoEdge;
-}
-
-// Decision from a code against thr2: 0 or 1 when the code's bracket lies
-// wholly on one side of thr2, 2 when thr2 falls inside the bracket (the
-// exact G^2 must then be recomputed).
-__device__ __forceinline__ uint32_t code16_decide(uint32_t c, float thr2) {
-    if (c & 0x8000u) return 0u;
-    const float lo = __uint_as_float(c << 16);
-    const float hi = __uint_as_float((c + 1u) << 16);
-    return lo > thr2 ? 1u : (hi <= thr2 ? 0u : 2u);
+// Pass-1 store code: G^2 where Z = 1, else -1 (never above a threshold).
+__device__ __forceinline__ float pass1_code(bool z, float g2) {
+    return z ? g2 : -1.0f;
 }
 
 // Threshold on G^2: tau = theta * sqrt(M2), compare G^2 > tau^2.

@@ -19,8 +19,9 @@ enum SweepMode : int {
 };
 
 // One image as the kernels see it.  Pitches are in elements of the
-// respective buffer.  fout: B (BG) or L (BGL); g2: G^2 (BG, BGL); fout/g2
-// rows use pitch `op`, a multiple of 4 floats with 16-byte aligned rows.
+// respective buffer.  fout: pass-1 code (STORE), B (BG) or L (BGL);
+// g2: G^2 (BG, BGL).  fout/g2 rows use pitch `op`, which is a multiple of
+// 4 floats with 16-byte aligned rows.
 struct ImgArgs {
     const float* src;
     int64_t sp;
@@ -31,8 +32,6 @@ struct ImgArgs {
     int64_t op;
     uint32_t* slot;   // max G^2 bits of this image
     float* dmax;      // optional: receives M = sqrt(max G^2)
-    uint16_t* code;   // STORE pass-1 codes, rows of pitch cp (a multiple of 8)
-    int64_t cp;
     int32_t H, W;
 };
 
@@ -56,11 +55,8 @@ bool sweep_supported(int ks, int c, int ty);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sweep(int mode, int ks, int c, int ty, const ImgArgs& a,
                         const Taps& t, float theta, hipStream_t s);
-// Pass 2 of STORE: code -> mask (exact recompute where a code is too
-// close to the threshold), and M into dmax.  exact_all: recompute every
-// edge pixel (a self-check of the fallback).
-hipError_t launch_threshold_code(const ImgArgs& a, const Taps& t, int ks, float theta,
-                                 int exact_all, hipStream_t s);
+// Pass 2 of STORE: code -> mask, and M into dmax.
+hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s);
 // Write M into a.dmax from a.slot (one thread).
 hipError_t launch_write_max(const ImgArgs& a, hipStream_t s);
 
@@ -107,8 +103,7 @@ struct BatchHeader {
     int32_t n_items2;
     int32_t pass_mode;  // HX_PASS_STORE / HX_PASS_RECOMPUTE
     float theta;
-    int32_t exact_all;  // pass 2 recomputes every edge pixel exactly
-    int32_t pad[2];
+    int32_t pad[3];
 };
 
 size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2);

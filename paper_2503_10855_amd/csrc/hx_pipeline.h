@@ -99,9 +99,6 @@ struct hx_pipeline {
     hipStream_t capture_stream = nullptr;
     int batch_grid[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [pass mode][phase - 1]
     bool timing = false;
-    // Pass 2 recomputes every edge pixel's G^2 exactly instead of deciding
-    // from its 16-bit code (HX_EXACT_CODES set at creation; a self-check).
-    int exact_all = 0;
     int last_timed_ctx = -1;
 };
 

@@ -21,14 +21,20 @@
 
 namespace hx {
 
-constexpr int kBC = 4;    // columns per lane of the batch sweep
-constexpr int kBTY = 64;  // rows per sweep tile
+#ifndef HX_BATCH_C
+#define HX_BATCH_C 4
+#endif
+#ifndef HX_BATCH_TY
+#define HX_BATCH_TY 64
+#endif
+constexpr int kBC = HX_BATCH_C;    // columns per lane of the batch sweep
+constexpr int kBTY = HX_BATCH_TY;  // rows per sweep tile
 
 int batch_sweep_c() { return kBC; }
 int batch_sweep_ty() { return kBTY; }
 
 __host__ __device__ inline int p2_rows(int64_t W) {
-    const int64_t r = 8192 / (W > 0 ? W : 1);
+    const int64_t r = 4096 / (W > 0 ? W : 1);
     return r < 1 ? 1 : (r > (1 << 20) ? (1 << 20) : (int)r);
 }
 int batch_p2_rows(int64_t W) { return p2_rows(W); }
@@ -102,12 +108,11 @@ __global__ __launch_bounds__(256) void k_batch_p2(const uint8_t* __restrict__ ta
             const int rb = p2_rows(a.W);
             const int r0 = it.local * rb;
             const int r1 = min(a.H, r0 + rb);
-            const int wq = (a.W + 7) / 8;
+            const int wq = (a.W + 3) / 4;
             const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &
                               ((a.mp % 4) == 0);
             for (int y = r0; y < r1; ++y)
-                for (int q = lane; q < wq; q += 64)
-                    threshold8(a, tp, KS, y, q * 8, thr2, mvec, tv.hdr.exact_all != 0);
+                for (int q = lane; q < wq; q += 64) threshold4(a, y, q * 4, thr2, mvec);
         } else {
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             float unused = 0.0f;

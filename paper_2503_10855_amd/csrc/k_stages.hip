@@ -171,20 +171,19 @@ __global__ __launch_bounds__(256) void k_threshold_zg(ImgArgs a, StageBufs b,
     }
 }
 
-// Pass 2 of STORE on one image: code -> mask, 8 pixels per thread.
-__global__ __launch_bounds__(256) void k_threshold_code(ImgArgs a, Taps t, int ks,
-                                                       float theta, int exact_all) {
+// Pass 2 of STORE on one image: code -> mask, 4 pixels per thread.
+__global__ __launch_bounds__(256) void k_threshold_code(ImgArgs a, float theta) {
     const uint32_t m2 = *a.slot;
     const float thr2 = thr2_from(m2, theta);
     if (a.dmax && blockIdx.x == 0 && threadIdx.x == 0) *a.dmax = max_from(m2);
-    const int wq = (a.W + 7) / 8;
+    const int wq = (a.W + 3) / 4;
     const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
     const int64_t total = (int64_t)wq * a.H;
     for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * 256) {
         const int y = (int)(g / wq);
-        const int x = (int)(g - (int64_t)y * wq) * 8;
-        threshold8(a, t, ks, y, x, thr2, mvec, exact_all != 0);
+        const int x = (int)(g - (int64_t)y * wq) * 4;
+        threshold4(a, y, x, thr2, mvec);
     }
 }
 
@@ -290,11 +289,10 @@ hipError_t launch_threshold_zg(const ImgArgs& a, const StageBufs& b,
     return hipGetLastError();
 }
 
-hipError_t launch_threshold_code(const ImgArgs& a, const Taps& t, int ks, float theta,
-                                 int exact_all, hipStream_t s) {
-    const int64_t work = (int64_t)((a.W + 7) / 8) * a.H;
+hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s) {
+    const int64_t work = (int64_t)((a.W + 3) / 4) * a.H;
     hipLaunchKernelGGL(k_threshold_code, dim3(stream_grid(work, 256 * 4)), dim3(256), 0, s,
-                       a, t, ks, theta, exact_all);
+                       a, theta);
     return hipGetLastError();
 }
 

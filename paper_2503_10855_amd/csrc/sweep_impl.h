@@ -45,7 +45,10 @@ struct SweepShape {
     static constexpr int NS = TY + 2 * HX;                 // steps
     static constexpr int NP = 2 * R + 4;                   // pipeline fill
     static constexpr int P = 8;                            // ring period
-    static constexpr int PF = 4;                           // prefetch rows
+#ifndef HX_SWEEP_PF
+#define HX_SWEEP_PF 6
+#endif
+    static constexpr int PF = HX_SWEEP_PF;                 // prefetch rows
     static constexpr bool NEED_L =
         MODE == SM_STORE || MODE == SM_MASK || MODE == SM_BGL;
     static constexpr bool NEED_Z = MODE == SM_STORE || MODE == SM_MASK;
@@ -329,23 +332,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                 z[e] = zero_cross(max3f(hmx[J2][e], hmx[J1][e], hmx[J][e]),
                                                   min3f(hmn[J2][e], hmn[J1][e], hmn[J][e]));
                             if constexpr (MODE == SM_STORE) {
-                                uint32_t code[C];
+                                float code[C];
 #pragma unroll
-                                for (int e = 0; e < C; ++e) code[e] = pass1_code16(z[e], g2d[e]);
-                                const gptr<uint16_t> cp =
-                                    as_global(a.code) + (int64_t)vz * a.cp + cbase;
-                                if constexpr (!BX && C % 2 == 0) {
-                                    if (lane_out) {
-#pragma unroll
-                                        for (int e = 0; e < C; e += 2)
-                                            ((gptr<uint32_t>)cp)[e / 2] =
-                                                code[e] | (code[e + 1] << 16);
-                                    }
-                                } else {
-#pragma unroll
-                                    for (int e = 0; e < C; ++e)
-                                        if (ecol[e]) cp[e] = (uint16_t)code[e];
-                                }
+                                for (int e = 0; e < C; ++e) code[e] = pass1_code(z[e], g2d[e]);
+                                store_f(a.fout, vz, code);
                             } else {
                                 const gptr<uint8_t> rp =
                                     as_global(a.mask) + (int64_t)vz * a.mp + cbase;

@@ -227,31 +227,3 @@ def test_abi_rejects_bad_arguments(hx):
         assert int((mask != 5).sum()) == 0  # nothing was enqueued
     with pytest.raises(hx.HxError):
         hx.Pipeline(ksize=9).set_schedule(256, 64, 4)
-
-
-@pytest.mark.parametrize("ks,sigma", [(5, 1.0), (7, 1.5)])
-def test_code16_fallback_matches_fast_path(hx, ks, sigma):
-    """Pass 1 stores G^2 truncated to 16 bits; pass 2 decides from the
-    truncation bracket and recomputes G^2 exactly only when the threshold
-    falls inside it.  Forcing the exact recompute for every edge pixel must
-    give the same masks (per image and batched)."""
-    sizes = [(130, 517), (1, 1), (300, 61), (1080, 1920)]
-    imgs = [synth.image(h, w, 26, i) for i, (h, w) in enumerate(sizes)]
-    srcs = [dev(a) for a in imgs]
-    out = {}
-    for exact in (False, True):
-        if exact:
-            os.environ["HX_EXACT_CODES"] = "1"
-        try:
-            with hx.Pipeline(ksize=ks, sigma=sigma, theta=THETA) as p:
-                print(f"code16 exact_all={exact}: launching", flush=True)
-                per = [p.edge_detect(s).cpu().numpy() for s in srcs]
-                bat = [m.cpu().numpy() for m in p.edge_detect_batched(srcs)]
-                p.sync()
-        finally:
-            os.environ.pop("HX_EXACT_CODES", None)
-        out[exact] = (per, bat)
-    for i in range(len(imgs)):
-        assert np.array_equal(out[False][0][i], out[True][0][i]), i
-        assert np.array_equal(out[False][1][i], out[True][1][i]), i
-        assert np.array_equal(out[False][0][i], out[False][1][i]), i
