@@ -24,9 +24,13 @@ if ROOT not in sys.path:
 METRIC = ("Mpixel/s and %HBM-roofline, batched vs per-image; "
           "p50/p99 latency at QPS")
 HBM_PEAK_GBS = 8000.0
-PASS1_BYTES_PER_PX = 4.0   # input read once (algorithmic)
 PATH_BYTES_PER_PX = 5.0    # input read once + mask written once
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_pass1.json")
+# Algorithmic bytes per pixel of each batched kernel, by pass structure:
+# STORE's pass 1 reads the input (its 4 B/px code is an intermediate, not
+# algorithmic) and its pass 2 writes the mask; RECOMPUTE's pass 1 reads the
+# input for the maximum and its pass 2 reads it again and writes the mask.
+KERNEL_BYTES_PER_PX = {1: {1: 4.0, 2: 1.0}, 2: {1: 4.0, 2: 5.0}}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_64x1080p.json")
 SWEEP_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in
                  ("sweep_impl.h", "hx_device.h", "k_batch.hip", "thresh_impl.h")]
 
@@ -45,8 +49,8 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(pixels):
-    """HBM bytes per pass-1 launch from the committed rocprofv3 counter
+def measured_traffic(kernel, pixels):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when absent or taken on different kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -55,26 +59,35 @@ def measured_traffic(pixels):
         return None
     if t.get("source_hash") != source_hash() or t.get("pixels") != pixels:
         return None
-    return t.get("bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, images, budget_s=20.0):
-    """The oracle (plain fp64 C) on a bounded sample of the workload."""
+def cpu_baseline(wl, images, budget_s=12.0):
+    """The oracle (plain fp64 C) on a bounded sample of the workload: whole
+    passes over its images, one image per thread, repeated to about
+    `budget_s` seconds of wall time."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
     oracle.edge_detect(images[0], wl.ksize, wl.sigma, wl.theta)
     one = time.perf_counter() - t0
-    n = int(max(1, min(len(images), budget_s / max(one, 1e-6))))
+    # Workloads with many large images are cut to a prefix of about the budget.
+    n = int(max(1, min(len(images), budget_s * min(threads, len(images)) / max(one, 1e-6))))
     sample = images[:n]
     t0 = time.perf_counter()
     oracle.edge_detect_many(sample, wl.ksize, wl.sigma, wl.theta, nthreads=threads)
+    first = time.perf_counter() - t0
+    reps = int(max(1, budget_s / max(first, 1e-6)))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.edge_detect_many(sample, wl.ksize, wl.sigma, wl.theta, nthreads=threads)
     dt = time.perf_counter() - t0
-    px = sum(a.shape[0] * a.shape[1] for a in sample)
+    px = reps * sum(a.shape[0] * a.shape[1] for a in sample)
     return {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": min(threads, n),
             "kind": "oracle",
-            "sample": f"{n} of {len(images)} images of the workload, one image per "
-                      f"thread, fp64 C oracle, {dt:.2f} s wall"}
+            "sample": f"{reps} passes over {n} of {len(images)} images of the workload, "
+                      f"one image per thread, fp64 C oracle, {dt:.2f} s wall"}
 
 
 def timed(fn, steps, warmup, sync):
@@ -99,7 +112,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="batch", choices=("batch", "serve", "reduce"),
+                    help="batch: the batched step (default); serve: the continuous-"
+                         "batching server under Poisson arrivals; reduce: the "
+                         "max-reduction ablation on the unfused per-image form")
     ap.add_argument("--workload", default="batch-64x1080p", choices=sorted(workloads()))
+    ap.add_argument("--requests", type=int, default=20000, help="serve: requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
+    ap.add_argument("--budget-mb", type=int, default=32 * 1024, help="serve: HBM budget")
+    ap.add_argument("--streams", type=int, default=4, help="serve: compute streams")
+    ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
+    ap.add_argument("--images-reduce", type=int, default=8,
+                    help="reduce: 1920x1080 images per step")
     ap.add_argument("--pass-mode", type=int, default=0, choices=(0, 1, 2))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-per-image", action="store_true",
@@ -124,6 +148,11 @@ def main():
         build()
     from paper_2503_10855_amd import hx
 
+    if args.mode == "serve":
+        return run_serve(args, hx)
+    if args.mode == "reduce":
+        return run_reduce(args, hx)
+
     wl = workloads()[args.workload]()
     images = [wl.image(i) for i in range(len(wl.sizes))]
     srcs = [torch.from_numpy(a).cuda() for a in images]
@@ -145,7 +174,7 @@ def main():
         value = pixels / (ms_step * 1e-3) / 1e6
 
         # The same kernels launched directly with events around each one
-        # (timing mode): durations of pass 1, the dominant kernel.
+        # (timing mode): durations of the reset and the two passes.
         p.set_timing(True)
         for _ in range(args.warmup):
             batched()
@@ -179,8 +208,35 @@ def main():
                 "masks_identical_to_batched": bool(same),
             }
 
-    achieved = PASS1_BYTES_PER_PX * pixels / (ms_p1 * 1e-3) / 1e9
-    traffic = measured_traffic(pixels)
+        # Per-call latency of the per-image forms on the first image:
+        # events around each single call, 200 calls after a warm-up.
+        lat = {}
+        for name, sch in (("fused", None), ("plain", (64, 16, 1))):
+            if sch:
+                p.set_schedule(*sch)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(200)]
+            for _ in range(10):
+                p.edge_detect(srcs[0], masks[0])
+            sync()
+            for a, b in ev:
+                a.record()
+                p.edge_detect(srcs[0], masks[0])
+                b.record()
+                sync()
+            v = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
+            lat[name] = dict(percentiles(v), mean=round(float(v.mean()) * 1e3, 4),
+                             shape=list(wl.sizes[0]))
+        p.set_schedule()
+
+    # The dominant kernel is the longer of the two passes.
+    pm = args.pass_mode or 2
+    dom = 1 if ms_p1 >= ms_p2 else 2
+    ms_dom = ms_p1 if dom == 1 else ms_p2
+    bpp = KERNEL_BYTES_PER_PX[pm][dom]
+    kname = f"k_batch_p{dom}<{wl.ksize}, {pm}>"
+    achieved = bpp * pixels / (ms_dom * 1e-3) / 1e9
+    traffic = measured_traffic(kname, pixels)
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -200,11 +256,11 @@ def main():
                    "pass_mode": {0: "recompute (batch default)", 1: "store",
                                  2: "recompute"}[args.pass_mode],
                    "per_image_schedule": list(sched)},
-        "roofline": {"kernel": "pass 1 (fused sweep, k_batch_p1)", "bound": "hbm",
+        "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "ms_per_launch": round(ms_p1, 4),
-                     "bytes_per_px": PASS1_BYTES_PER_PX},
+                     "traffic": traffic, "ms_per_launch": round(ms_dom, 4),
+                     "bytes_per_px": bpp, "pixels_per_launch": pixels},
         "path_roofline": {"achieved": round(PATH_BYTES_PER_PX * pixels / (ms_step * 1e-3) / 1e9, 1),
                           "unit": "GB/s", "bytes_per_px": PATH_BYTES_PER_PX,
                           "frac": round(PATH_BYTES_PER_PX * pixels / (ms_step * 1e-3)
@@ -212,6 +268,7 @@ def main():
         "kernels_ms": {"reset": round(ms_reset, 4), "pass1": round(ms_p1, 4),
                        "pass2": round(ms_p2, 4)},
         "per_image": per_image,
+        "per_call_latency_ms": lat,
         "wall_s": round(wall, 3),
     }
     # A plain 1 GiB device-to-device copy: the practical HBM ceiling.
@@ -232,6 +289,150 @@ def main():
         line["calib_copy_bytes"] = nbytes
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, images)
+    print(json.dumps(line), flush=True)
+
+
+def percentiles(v, qs=(50, 99)):
+    import numpy as np
+    return {f"p{q}": round(float(np.percentile(v, q)) * 1e3, 4) for q in qs}
+
+
+def run_serve(args, hx):
+    """Continuous batching: requests (crops of a pool of 4096x4096 images,
+    sides log-uniform in [64, 4096]) arrive as a Poisson process and are
+    submitted at their scheduled times; latency runs from the scheduled
+    arrival until the mask is in host memory."""
+    import numpy as np
+    import torch
+    from paper_2503_10855_amd import synth
+
+    n = args.requests
+    print(f"serve: generating the request pool ({synth.SERVING_POOL} x "
+          f"{synth.SERVING_POOL_SIDE}^2)", file=sys.stderr, flush=True)
+    pool = synth.serving_pool()
+    reqs = synth.serving_requests(n)
+    arrivals = synth.poisson_arrivals(n, args.rate)
+    views = [pool[j][y0:y0 + h, x0:x0 + w] for j, y0, x0, h, w in reqs]
+    total_px = sum(h * w for *_, h, w in reqs)
+    budget = args.budget_mb << 20
+    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    with hx.Pipeline(ksize=5, sigma=1.0, theta=0.1, max_pixels=1 << 26,
+                     max_images=args.max_batch) as p:
+        with hx.Server(p, hbm_budget=budget, streams=args.streams,
+                       max_batch=args.max_batch, arena=arena) as srv:
+            # Warm-up: every batch context captures its graph once.
+            warm = [srv.submit(views[i]) for i in range(64)]
+            for t, i in zip(warm, range(64)):
+                while srv.poll(t, views[i].shape) is None:
+                    time.sleep(1e-4)
+            st0 = srv.stats()
+            print(f"serve: {n} requests at {args.rate:g}/s, budget {args.budget_mb} MiB",
+                  file=sys.stderr, flush=True)
+            lat = np.zeros(n)
+            svc = np.zeros(n)
+            outs = {}
+            pending = {}
+            t0 = srv.now() + 0.05
+            i = done = 0
+            next_report = 1.0
+            while done < n:
+                now = srv.now()
+                while i < n and t0 + arrivals[i] <= now:
+                    t = srv.submit(views[i], arrival=t0 + arrivals[i])
+                    pending[t] = (i, np.empty(views[i].shape, np.uint8))
+                    i += 1
+                for t in list(pending):
+                    k, buf = pending[t]
+                    r = srv.poll_timed(t, buf.shape, out=buf)
+                    if r is not None:
+                        lat[k], svc[k] = r[1], r[2]
+                        if k % 500 == 0:
+                            outs[k] = buf
+                        del pending[t]
+                        done += 1
+                if now - t0 > next_report:
+                    print(f"serve: {now - t0:.1f} s, {done} done, {len(pending)} pending",
+                          file=sys.stderr, flush=True)
+                    next_report += 1.0
+                if i < n and not pending:
+                    time.sleep(max(0.0, min(2e-4, t0 + arrivals[i] - srv.now())))
+            t_end = srv.now()
+            st = srv.stats()
+        # Served masks against the per-image call (bit-exact), on a sample.
+        same = True
+        for k, m in outs.items():
+            ref = p.edge_detect(torch.from_numpy(np.ascontiguousarray(views[k])).cuda())
+            same &= bool(np.array_equal(ref.cpu().numpy(), m))
+    span = t_end - t0
+    line = {
+        "metric": METRIC,
+        "value": round(total_px / span / 1e6, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serve-{n}-poisson-{args.rate:g}-64..4096-k5",
+                   "requests": n, "rate_per_s": args.rate, "pixels": total_px,
+                   "budget_mib": args.budget_mb, "streams": args.streams,
+                   "max_batch": args.max_batch},
+        "latency_ms": percentiles(lat),
+        "latency_ms_mean": round(float(lat.mean()) * 1e3, 3),
+        "service_ms": percentiles(svc),
+        "offered_mpx_s": round(total_px / arrivals[-1] / 1e6, 1),
+        "span_s": round(span, 3),
+        "batches": st["batches"] - st0["batches"],
+        "mean_batch": round(n / max(1, st["batches"] - st0["batches"]), 2),
+        "peak_arena_mib": round(st["peak_bytes"] / 2**20, 1),
+        "sample_masks_identical_to_per_image": same,
+        "sample": len(outs),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_reduce(args, hx):
+    """The max-reduction ablation: the unfused per-image form (one kernel
+    per stage) with three reductions of the gradient magnitude: the wave64
+    shuffle tree with one atomic per wave, a two-level tree (per-thread
+    partials, then one thread over them), and one thread scanning every
+    value."""
+    import numpy as np
+    import torch
+    from paper_2503_10855_amd import synth
+
+    wl = synth.batch_1080p(args.images_reduce)
+    imgs = [torch.from_numpy(wl.image(i)).cuda() for i in range(len(wl.sizes))]
+    masks = [torch.empty(a.shape, dtype=torch.uint8, device="cuda") for a in imgs]
+    sync = torch.cuda.synchronize
+    out = {}
+    ref = None
+    with hx.Pipeline(ksize=5, sigma=1.0, theta=0.1, max_pixels=wl.pixels,
+                     max_images=len(imgs)) as p:
+        for name, mode in (("tree", hx.REDUCE_TREE), ("two_level", hx.REDUCE_TWO_LEVEL),
+                           ("sequential", hx.REDUCE_SEQUENTIAL)):
+            p.set_schedule(64, 16, 1, hx.PASS_STORE, mode)
+            print(f"reduce: {name}", file=sys.stderr, flush=True)
+
+            def step():
+                for s, m in zip(imgs, masks):
+                    p.edge_detect(s, m)
+            steps = args.steps if mode != hx.REDUCE_SEQUENTIAL else max(1, args.steps // 10)
+            ms, _ = timed(step, steps, 1, sync)
+            got = [m.cpu() for m in masks]
+            if ref is None:
+                ref = got
+            out[name] = {"ms_per_step": round(ms, 4),
+                         "mpx_s": round(wl.pixels / (ms * 1e-3) / 1e6, 1),
+                         "same_masks": all(torch.equal(a, b) for a, b in zip(ref, got))}
+        p.set_schedule()
+    for v in out.values():
+        v["speedup_vs_sequential"] = round(out["sequential"]["ms_per_step"] / v["ms_per_step"], 2)
+    line = {"metric": "max-reduction ablation (unfused per-image EDGE)", "unit": "Mpixel/s",
+            "value": out["tree"]["mpx_s"], "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "images": len(imgs), "pixels": wl.pixels,
+                       "schedule": "64x16 tiles, fusion depth 1"},
+            "variants": out}
     print(json.dumps(line), flush=True)
 
 

@@ -234,6 +234,13 @@ hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h,
 hx_status hx_serve_poll(hx_server* s, uint64_t ticket, uint8_t* h_mask,
                         int64_t mask_pitch, double* latency_s);
 
+/* hx_serve_poll, also giving the request's service time (nullable): from
+ * the launch of its batch (copy-in enqueued) until its mask is on the host,
+ * i.e. the latency without the wait for admission and for a free stream. */
+hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
+                              int64_t mask_pitch, double* latency_s,
+                              double* service_s);
+
 /* Seconds on the server's monotonic clock. */
 double hx_serve_now(const hx_server* s);
 

@@ -95,7 +95,8 @@ struct Request {
     uint64_t id;
     int64_t h, w;
     double arrival;
-    double done_t = 0.0;
+    double launch_t = 0.0;  // the scheduler enqueued its batch's copy-in
+    double done_t = 0.0;    // its batch's mask copy-out completed
     ReqState state = QUEUED;
     size_t host_off = 0, host_bytes = 0;  // pinned: input then mask
     size_t dev_off = 0, dev_bytes = 0;    // arena: input then mask
@@ -173,8 +174,10 @@ void launch_batch(hx_server* s, std::unique_lock<std::mutex>& lk, int k,
     hipStream_t st = s->streams[k];
     std::vector<hx_image> imgs;
     imgs.reserve(batch.size());
+    const double t_launch = now_s(s);
     for (Request* r : batch) {
         r->state = LAUNCHED;
+        r->launch_t = t_launch;
         float* d_in = reinterpret_cast<float*>(s->arena + r->dev_off);
         uint8_t* d_mask = s->arena + r->dev_off + align_up(r->in_bytes());
         imgs.push_back(hx_image{d_in, r->h, r->w, r->w, d_mask, r->w});
@@ -354,6 +357,11 @@ hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h, int64_t w
 
 hx_status hx_serve_poll(hx_server* s, uint64_t ticket, uint8_t* h_mask, int64_t mask_pitch,
                         double* latency_s) {
+    return hx_serve_poll_timed(s, ticket, h_mask, mask_pitch, latency_s, nullptr);
+}
+
+hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
+                              int64_t mask_pitch, double* latency_s, double* service_s) {
     if (!s) return fail(HX_E_INVALID, "NULL server");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
@@ -372,6 +380,7 @@ hx_status hx_serve_poll(hx_server* s, uint64_t ticket, uint8_t* h_mask, int64_t 
             std::memcpy(h_mask + y * mask_pitch, src + y * r->w, (size_t)r->w);
     }
     if (latency_s) *latency_s = r->done_t - r->arrival;
+    if (service_s) *service_s = r->done_t - r->launch_t;
     s->host_alloc->release(r->host_off, r->host_bytes);
     s->reqs.erase(it);
     s->host_cv.notify_all();

@@ -77,6 +77,9 @@ _SIGS = {
                                        ctypes.POINTER(_u64)]),
     "hx_serve_poll": (ctypes.c_int, [_P, _u64, _P, _i64,
                                      ctypes.POINTER(ctypes.c_double)]),
+    "hx_serve_poll_timed": (ctypes.c_int, [_P, _u64, _P, _i64,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]),
     "hx_serve_now": (ctypes.c_double, [_P]),
     "hx_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                       ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
@@ -288,26 +291,42 @@ class Server:
         return _lib.hx_serve_now(self._h)
 
     def submit(self, img, arrival=None):
-        """img: host float32 numpy array (H, W).  Returns a ticket."""
+        """img: host float32 numpy array (H, W); a row-strided view (a crop)
+        is passed with its pitch, without a copy.  Returns a ticket."""
         import numpy as np
-        a = np.ascontiguousarray(img, dtype=np.float32)
+        a = img
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.ndim == 2
+                and a.strides[1] == 4 and a.strides[0] % 4 == 0
+                and a.strides[0] >= 4 * a.shape[1]):
+            a = np.ascontiguousarray(a, dtype=np.float32)
         t = _u64()
         _check(_lib.hx_serve_submit(self._h, a.ctypes.data, a.shape[0], a.shape[1],
-                                    a.shape[1], self.now() if arrival is None else arrival,
+                                    a.strides[0] // 4,
+                                    self.now() if arrival is None else arrival,
                                     ctypes.byref(t)), "hx_serve_submit")
         return t.value
 
-    def poll(self, ticket, shape):
-        """Returns (mask, latency_s) when done, or None while pending."""
+    def poll(self, ticket, shape, out=None):
+        """Returns (mask, latency_s) when done, or None while pending.  `out`
+        (uint8, C-contiguous, of `shape`) receives the mask if given."""
+        r = self.poll_timed(ticket, shape, out)
+        return None if r is None else r[:2]
+
+    def poll_timed(self, ticket, shape, out=None):
+        """Returns (mask, latency_s, service_s) when done, or None while
+        pending; service_s runs from the batch's launch to the mask on the host."""
         import numpy as np
-        m = np.empty(shape, dtype=np.uint8)
+        m = np.empty(shape, dtype=np.uint8) if out is None else out
+        if m.shape != tuple(shape) or m.dtype != np.uint8 or not m.flags.c_contiguous:
+            raise ValueError("out must be a C-contiguous uint8 array of the request's shape")
         lat = ctypes.c_double()
-        st = _lib.hx_serve_poll(self._h, ticket, m.ctypes.data, shape[1],
-                                ctypes.byref(lat))
+        svc = ctypes.c_double()
+        st = _lib.hx_serve_poll_timed(self._h, ticket, m.ctypes.data, shape[1],
+                                      ctypes.byref(lat), ctypes.byref(svc))
         if st == HX_E_PENDING:
             return None
-        _check(st, "hx_serve_poll")
-        return m, lat.value
+        _check(st, "hx_serve_poll_timed")
+        return m, lat.value, svc.value
 
     def stats(self):
         v = [_u64() for _ in range(4)]

@@ -113,3 +113,28 @@ def poisson_arrivals(n: int, rate: float, seed: int = SEED_SERVING):
     """n arrival times (seconds) of a Poisson process of the given rate."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 1]))
     return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+SERVING_POOL = 16
+SERVING_POOL_SIDE = 4096
+
+
+def serving_pool(n: int = SERVING_POOL, side: int = SERVING_POOL_SIDE):
+    """The pre-generated source images that serving requests are cut from
+    (generating a fresh image per request would cost more than serving it)."""
+    return [image(side, side, SEED_SERVING, 1000 + j, 16) for j in range(n)]
+
+
+def serving_requests(n: int = 20000, pool: int = SERVING_POOL,
+                     side: int = SERVING_POOL_SIDE):
+    """n requests as (pool index, y0, x0, h, w): the sizes of serving_sizes,
+    cut from a pool image at seeded offsets."""
+    sizes = serving_sizes(n)
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_SERVING, 2]))
+    out = []
+    for h, w in sizes:
+        j = int(rng.integers(0, pool))
+        y0 = int(rng.integers(0, side - h + 1))
+        x0 = int(rng.integers(0, side - w + 1))
+        out.append((j, y0, x0, h, w))
+    return out
