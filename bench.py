@@ -29,7 +29,9 @@ PATH_BYTES_PER_PX = 5.0    # input read once + mask written once
 # STORE's pass 1 reads the input (its 4 B/px code is an intermediate, not
 # algorithmic) and its pass 2 writes the mask; RECOMPUTE's pass 1 reads the
 # input for the maximum and its pass 2 reads it again and writes the mask.
-KERNEL_BYTES_PER_PX = {1: {1: 4.0, 2: 1.0}, 2: {1: 4.0, 2: 5.0}}
+# SPECULATE's pass 1 reads the input and writes the mask; its pass 2
+# touches only the listed pixels.
+KERNEL_BYTES_PER_PX = {1: {1: 4.0, 2: 1.0}, 2: {1: 4.0, 2: 5.0}, 3: {1: 5.0, 2: 0.0}}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_64x1080p.json")
 SWEEP_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in
                  ("sweep_impl.h", "hx_device.h", "k_batch.hip", "thresh_impl.h")]
@@ -124,7 +126,9 @@ def main():
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
     ap.add_argument("--images-reduce", type=int, default=8,
                     help="reduce: 1920x1080 images per step")
-    ap.add_argument("--pass-mode", type=int, default=0, choices=(0, 1, 2))
+    ap.add_argument("--pass-mode", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="batched pass structure: 0 default, 1 STORE, 2 RECOMPUTE, "
+                         "3 SPECULATE")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-per-image", action="store_true",
                     help="skip the per-image comparison forms")
@@ -179,12 +183,12 @@ def main():
         for _ in range(args.warmup):
             batched()
         p.last_timing()
-        acc = np.zeros(3)
+        acc = np.zeros(4)
         for _ in range(args.steps):
             batched()
             acc += np.array(p.last_timing())
         p.set_timing(False)
-        ms_reset, ms_p1, ms_p2 = (acc / args.steps).tolist()
+        ms_reset, ms_p1, ms_p2, ms_p0 = (acc / args.steps).tolist()
 
         per_image = None
         if not args.no_per_image:
@@ -253,8 +257,8 @@ def main():
         "config": {"workload": wl.name, "images": len(wl.sizes), "pixels": pixels,
                    "ksize": wl.ksize, "sigma": wl.sigma, "theta": wl.theta,
                    "form": "batched graph launch",
-                   "pass_mode": {0: "recompute (batch default)", 1: "store",
-                                 2: "recompute"}[args.pass_mode],
+                   "pass_mode": {0: "batch default", 1: "store", 2: "recompute",
+                                 3: "speculate"}[args.pass_mode],
                    "per_image_schedule": list(sched)},
         "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -265,8 +269,8 @@ def main():
                           "unit": "GB/s", "bytes_per_px": PATH_BYTES_PER_PX,
                           "frac": round(PATH_BYTES_PER_PX * pixels / (ms_step * 1e-3)
                                         / 1e9 / HBM_PEAK_GBS, 4)},
-        "kernels_ms": {"reset": round(ms_reset, 4), "pass1": round(ms_p1, 4),
-                       "pass2": round(ms_p2, 4)},
+        "kernels_ms": {"reset": round(ms_reset, 4), "pass0": round(ms_p0, 4),
+                       "pass1": round(ms_p1, 4), "pass2": round(ms_p2, 4)},
         "per_image": per_image,
         "per_call_latency_ms": lat,
         "wall_s": round(wall, 3),

@@ -65,8 +65,17 @@ typedef struct hx_server hx_server;
  *  STORE:      pass 1 computes every stage and stores one float per pixel
  *              (G^2 where Z = 1, else -1) plus the max; pass 2 thresholds.
  *  RECOMPUTE:  pass 1 computes blur and Sobel only, for the max; pass 2
- *              recomputes every stage and writes the mask directly. */
-enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2 };
+ *              recomputes every stage and writes the mask directly.
+ *  SPECULATE:  pass 0 computes G^2 on sampled row bands (16 rows in every
+ *              128) for a lower bound m <= max G^2 of each image; pass 1
+ *              computes every stage once, writes the mask against the
+ *              threshold of m (a pixel it leaves at 0 is 0 under the true
+ *              max too) and lists the pixels it set, with their G^2;
+ *              pass 2 re-decides only those against the true max.  Exact
+ *              for every input; fast when the listed pixels are few.  Runs
+ *              the 256 x 64 sweep tile only. */
+enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2,
+       HX_PASS_SPECULATE = 3 };
 
 /* Shape of the max reduction (the paper's reduction_tree schedule and its
  * warp-primitive refinement, Use and Impact of Schedules):
@@ -141,11 +150,12 @@ void hx_pipeline_destroy(hx_pipeline* p);
 hx_status hx_pipeline_sync(hx_pipeline* p);
 
 /* Timing mode, for benchmarks.  While enabled, batched calls launch their
- * three kernels (reset, pass 1, pass 2) directly instead of through the
+ * kernels (reset, [pass 0,] pass 1, pass 2) directly instead of through the
  * graph and bracket each with HIP events on the call's stream.
  * hx_pipeline_last_timing waits for the last batched call and returns the
- * three durations in milliseconds (ms[0] reset, ms[1] pass 1, ms[2]
- * pass 2).  HX_E_INVALID if no batched call ran in timing mode. */
+ * durations in milliseconds of its kernels in ms[0..3]: reset, pass 1,
+ * pass 2, and pass 0 (SPECULATE only, 0 otherwise; it runs between the
+ * reset and pass 1).  HX_E_INVALID if no batched call ran in timing mode. */
 hx_status hx_pipeline_set_timing(hx_pipeline* p, int enable);
 hx_status hx_pipeline_last_timing(hx_pipeline* p, float* ms);
 

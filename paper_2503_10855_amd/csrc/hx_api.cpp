@@ -100,8 +100,12 @@ hx_status validate_schedule(const hx_pipeline* p, const hx_schedule& s) {
         return fail(HX_E_INVALID, "sweep tile %dx%d not in {64,128,256}x{16,32,64,128}",
                     s.tile_w, s.tile_h);
     if (s.fusion_depth == 4 && s.pass_mode != HX_PASS_STORE &&
-        s.pass_mode != HX_PASS_RECOMPUTE)
+        s.pass_mode != HX_PASS_RECOMPUTE && s.pass_mode != HX_PASS_SPECULATE)
         return fail(HX_E_INVALID, "pass_mode %d unknown", s.pass_mode);
+    if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE &&
+        (s.tile_w != 64 * batch_sweep_c() || s.tile_h != batch_sweep_ty()))
+        return fail(HX_E_INVALID, "SPECULATE runs the %dx%d sweep tile only",
+                    64 * batch_sweep_c(), batch_sweep_ty());
     return HX_OK;
 }
 
@@ -121,6 +125,13 @@ hx_schedule choose_schedule(const hx_pipeline* p, int64_t H, int64_t W) {
     if (p->prm.tile_w) s.tile_w = p->prm.tile_w;
     if (p->prm.tile_h) s.tile_h = p->prm.tile_h;
     if (p->prm.pass_mode) s.pass_mode = p->prm.pass_mode;
+    // SPECULATE runs the batch sweep's tile; a tuned tile of another shape
+    // gives way to it unless the tile was fixed at creation.
+    if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE && !p->prm.tile_w &&
+        !p->prm.tile_h) {
+        s.tile_w = 64 * batch_sweep_c();
+        s.tile_h = batch_sweep_ty();
+    }
     return s;
 }
 
@@ -164,6 +175,9 @@ static ImgArgs base_args(const hx_image* img, uint32_t* slot, float* d_max) {
 
 hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
                     const hx_schedule& s, hipStream_t stream) {
+    // SPECULATE runs the batch kernels on a batch of one.
+    if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE)
+        return run_batched(p, img, 1, d_max, HX_PASS_SPECULATE, stream);
     ImgArgs a = base_args(img, p->slot1, d_max);
     const size_t plane = (size_t)a.H * (size_t)a.op;
     const float theta = p->prm.thresh_frac;
@@ -238,12 +252,15 @@ static hx_status ctx_init(hx_pipeline* p, BatchContext& c) {
 }
 
 static void ctx_release(BatchContext& c) {
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
         if (c.exec[i]) (void)hipGraphExecDestroy(c.exec[i]);
         if (c.graph[i]) (void)hipGraphDestroy(c.graph[i]);
     }
     c.table.release();
     c.code.release();
+    c.cand_code.release();
+    c.cand_row.release();
+    c.cand_n.release();
     if (c.h_table) (void)hipHostFree(c.h_table);
     if (c.slots) (void)hipFree(c.slots);
     if (c.ev_done) (void)hipEventDestroy(c.ev_done);
@@ -259,25 +276,28 @@ hx_status ctx_wait(BatchContext& c) {
     return HX_OK;
 }
 
-// Enqueue [reset, pass 1, pass 2] for this context on stream s; with
-// `timed`, bracket each launch with the context's timing events.
+// Enqueue [reset, (pass 0,) pass 1, pass 2] for this context on stream s;
+// with `timed`, bracket each launch with the context's timing events
+// (ev_t: 0 reset 1 pass-0 4 pass-1 2 pass-2 3).
 static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipStream_t s,
                                  bool timed = false) {
+    const int ks = p->prm.ksize;
     hipError_t e = timed ? hipEventRecord(c.ev_t[0], s) : hipSuccess;
     if (e == hipSuccess) e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[1], s);
+    if (e == hipSuccess && pass == HX_PASS_SPECULATE)
+        e = launch_batch_phase(ks, pass, 0, c.table.ptr, p->taps, p->batch_grid[pass][0], s);
+    if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[4], s);
     if (e == hipSuccess)
-        e = launch_batch_phase(p->prm.ksize, pass, 1, c.table.ptr, p->taps,
-                               p->batch_grid[pass][0], s);
+        e = launch_batch_phase(ks, pass, 1, c.table.ptr, p->taps, p->batch_grid[pass][1], s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[2], s);
     if (e == hipSuccess)
-        e = launch_batch_phase(p->prm.ksize, pass, 2, c.table.ptr, p->taps,
-                               p->batch_grid[pass][1], s);
+        e = launch_batch_phase(ks, pass, 2, c.table.ptr, p->taps, p->batch_grid[pass][2], s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[3], s);
     return e;
 }
 
-// Capture the three launches once per (context, pass mode, table address).
+// Capture the launches once per (context, pass mode, table address).
 static hx_status ctx_graph(hx_pipeline* p, BatchContext& c, int pass) {
     if (c.exec[pass] && c.graph_table[pass] == c.table.ptr) return HX_OK;
     if (c.exec[pass]) {
@@ -317,11 +337,14 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
     const int ks = p->prm.ksize;
     const SweepGeom geo{ks, batch_sweep_c(), batch_sweep_ty()};
     std::lock_guard<std::mutex> lk(p->batch_mu);
-    if (p->batch_grid[pass][0] <= 0) {
-        p->batch_grid[pass][0] = batch_grid_size(p->device, ks, pass, 1);
-        p->batch_grid[pass][1] = batch_grid_size(p->device, ks, pass, 2);
-        if (p->batch_grid[pass][0] <= 0 || p->batch_grid[pass][1] <= 0)
-            return fail(HX_E_HIP, "cannot size the batched launch");
+    if (pass < HX_PASS_STORE || pass > HX_PASS_SPECULATE)
+        return fail(HX_E_INVALID, "pass_mode %d unknown", pass);
+    if (p->batch_grid[pass][1] <= 0) {
+        for (int ph = pass == HX_PASS_SPECULATE ? 0 : 1; ph < 3; ++ph) {
+            p->batch_grid[pass][ph] = batch_grid_size(p->device, ks, pass, ph);
+            if (p->batch_grid[pass][ph] <= 0)
+                return fail(HX_E_HIP, "cannot size the batched launch");
+        }
     }
     BatchContext& c = p->ctx[p->next_ctx];
     p->next_ctx = (p->next_ctx + 1) % hx_pipeline::kContexts;
@@ -360,21 +383,30 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
                              hipStream_t stream) {
     c.last_pass = -1;  // the device table is stale until the copy is queued
     // Item counts and pass-1 store offsets.
-    std::vector<int64_t> tiles(n), p2n(n), off(n);
-    int64_t n1 = 0, n2 = 0, code_elems = 0;
+    const bool spec = pass == HX_PASS_SPECULATE;
+    std::vector<int64_t> tiles(n), p2n(n), p0n(n), off(n);
+    int64_t n1 = 0, n2 = 0, n0 = 0, code_elems = 0;
     for (int i = 0; i < n; ++i) {
         tiles[i] = geo.tiles(imgs[i].height, imgs[i].width);
         const int64_t rb = batch_p2_rows(imgs[i].width);
         p2n[i] = pass == HX_PASS_STORE ? (imgs[i].height + rb - 1) / rb : tiles[i];
+        p0n[i] = spec ? batch_sample_items(geo.ks, imgs[i].height, imgs[i].width) : 0;
         n1 += tiles[i];
         n2 += p2n[i];
+        n0 += p0n[i];
         off[i] = code_elems;
         if (pass == HX_PASS_STORE) code_elems += imgs[i].height * round4(imgs[i].width);
     }
-    if (n1 >= (int64_t(1) << 31) || n2 >= (int64_t(1) << 31))
+    if (n1 >= (int64_t(1) << 31) || n2 >= (int64_t(1) << 31) || n0 >= (int64_t(1) << 31))
         return fail(HX_E_INVALID, "batch has too many work items");
     if (pass == HX_PASS_STORE) HX_TRY(c.code.ensure((size_t)code_elems * sizeof(float)));
-    const size_t bytes = batch_table_bytes(n, n1, n2);
+    if (spec) {
+        const size_t entries = (size_t)n1 * batch_spec_entries();
+        HX_TRY(c.cand_code.ensure(entries * geo.c * sizeof(float)));
+        HX_TRY(c.cand_row.ensure(entries * sizeof(int32_t)));
+        HX_TRY(c.cand_n.ensure((size_t)n1 * 64 * sizeof(uint32_t)));
+    }
+    const size_t bytes = batch_table_bytes(n, n1, n2, n0);
     HX_TRY(c.table.ensure(bytes));
     if (c.h_table_bytes < bytes) {
         if (c.h_table) (void)hipHostFree(c.h_table);
@@ -392,6 +424,12 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
     hdr.n_items2 = (int32_t)n2;
     hdr.pass_mode = pass;
     hdr.theta = p->prm.thresh_frac;
+    hdr.n_items0 = (int32_t)n0;
+    if (spec) {
+        hdr.cand_code = (float*)c.cand_code.ptr;
+        hdr.cand_row = (int32_t*)c.cand_row.ptr;
+        hdr.cand_n = (uint32_t*)c.cand_n.ptr;
+    }
     std::memcpy(h, &hdr, sizeof hdr);
     ImgArgs* ia = (ImgArgs*)(h + sizeof(BatchHeader));
     for (int i = 0; i < n; ++i) {
@@ -403,6 +441,8 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
         for (int64_t t = 0; t < tiles[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
     for (int i = 0; i < n; ++i)
         for (int64_t t = 0; t < p2n[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
+    for (int i = 0; i < n; ++i)
+        for (int64_t t = 0; t < p0n[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
 
     HX_TRY(hipMemcpyAsync(c.table.ptr, h, bytes, hipMemcpyHostToDevice, stream));
     c.last_imgs.assign(imgs, imgs + n);
@@ -472,7 +512,6 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
     p->device = device;
     p->prm = prm;
     compute_taps(prm.ksize, prm.sigma, p->taps);
-    hx_schedule probe{prm.tile_w, prm.tile_h, prm.fusion_depth, prm.pass_mode, HX_REDUCE_TREE};
     if (prm.fusion_depth || prm.tile_w || prm.tile_h || prm.pass_mode) {
         hx_schedule s = choose_schedule(p, 1, 1);
         s.reduce_mode = HX_REDUCE_TREE;
@@ -482,7 +521,6 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
             return st;
         }
     }
-    (void)probe;
     DeviceGuard g(device);
     (void)hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     e = hipMalloc(&p->slot1, 64);
@@ -546,7 +584,10 @@ hx_status hx_pipeline_last_timing(hx_pipeline* p, float* ms) {
     if (p->last_timed_ctx < 0) return fail(HX_E_INVALID, "no batched call ran in timing mode");
     BatchContext& c = p->ctx[p->last_timed_ctx];
     HX_TRY(hipEventSynchronize(c.ev_t[3]));
-    for (int i = 0; i < 3; ++i) HX_TRY(hipEventElapsedTime(&ms[i], c.ev_t[i], c.ev_t[i + 1]));
+    HX_TRY(hipEventElapsedTime(&ms[0], c.ev_t[0], c.ev_t[1]));  // reset
+    HX_TRY(hipEventElapsedTime(&ms[1], c.ev_t[4], c.ev_t[2]));  // pass 1
+    HX_TRY(hipEventElapsedTime(&ms[2], c.ev_t[2], c.ev_t[3]));  // pass 2
+    HX_TRY(hipEventElapsedTime(&ms[3], c.ev_t[1], c.ev_t[4]));  // pass 0
     return HX_OK;
 }
 

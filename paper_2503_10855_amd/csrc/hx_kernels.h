@@ -16,6 +16,19 @@ enum SweepMode : int {
     SM_MASK = 2,     // every stage -> mask (reads the finished max)
     SM_BG = 3,       // blur + Sobel -> B, G^2, max
     SM_BGL = 4,      // blur + Sobel + Laplacian -> L, G^2, max
+    SM_SPEC = 5,     // every stage -> mask against a lower-bound threshold,
+                     // the list of pixels it set (SpecTile), and the max
+};
+
+// Where one SM_SPEC tile lists the pixels whose mask bit it set.  Entry
+// (j, lane) -- the lane's j-th listed row -- sits at index j * 64 + lane:
+// code[] holds G^2 of the lane's C pixels of that row, and row[] the row's
+// offset from the tile top times 16 plus a bit per column that was set.
+// n counts the entries of the calling lane.
+struct SpecTile {
+    float* code;     // C floats per entry
+    int32_t* row;
+    uint32_t n;
 };
 
 // One image as the kernels see it.  Pitches are in elements of the
@@ -101,12 +114,27 @@ struct BatchHeader {
     int32_t n_images;
     int32_t n_items1;
     int32_t n_items2;
-    int32_t pass_mode;  // HX_PASS_STORE / HX_PASS_RECOMPUTE
+    int32_t pass_mode;  // HX_PASS_STORE / RECOMPUTE / SPECULATE
     float theta;
-    int32_t pad[3];
+    int32_t n_items0;   // SPECULATE: sampled-band items of pass 0
+    int32_t pad[2];
+    // SPECULATE: the listed pixels of pass-1 item k occupy entries
+    // [k * 64 * TY, (k + 1) * 64 * TY) of cand_code / cand_row, and
+    // cand_n[k * 64 + lane] counts the lane's entries.
+    float* cand_code;
+    int32_t* cand_row;
+    uint32_t* cand_n;
+    void* pad2;
 };
 
-size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2);
+size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2,
+                         int64_t n_items0);
+// SPECULATE: pass-0 band geometry (16 sampled rows at the top of every 128)
+// and the listed-pixel capacity of one pass-1 item, in entries.
+constexpr int kSampleRows = 16;
+constexpr int kSampleStride = 128;
+int64_t batch_sample_items(int ks, int64_t H, int64_t W);
+int64_t batch_spec_entries();  // 64 * TY
 int batch_sweep_c();   // columns per lane of the batch sweep
 int batch_sweep_ty();  // rows per batch sweep tile
 // Rows per pass-2 item of the STORE threshold for width W.
@@ -115,8 +143,8 @@ int batch_p2_rows(int64_t W);
 // max_images.
 hipError_t launch_batch_reset(const void* d_table, uint32_t* slots,
                               int max_images, hipStream_t s);
-// One pass (phase 1 or 2) over the table's item list on `grid` persistent
-// workgroups.
+// One pass (phase 0, 1 or 2) over the table's item list on `grid`
+// persistent workgroups.  Phase 0 exists for SPECULATE only.
 hipError_t launch_batch_phase(int ks, int pass_mode, int phase,
                               const void* d_table, const Taps& t, int grid,
                               hipStream_t s);

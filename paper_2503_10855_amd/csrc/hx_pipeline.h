@@ -51,14 +51,15 @@ struct BatchContext {
     size_t h_table_bytes = 0;
     uint32_t* slots = nullptr;  // max_images max slots
     DevBuf code;                // pass-1 store buffer
+    DevBuf cand_code, cand_row, cand_n;  // SPECULATE: listed pixels
     hipEvent_t ev_done = nullptr;
-    hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};  // timing mode
+    hipEvent_t ev_t[5] = {};    // timing mode
     bool in_flight = false;
-    // Captured [reset, pass 1, pass 2] per pass mode, with the table
-    // address and grid sizes baked into the kernel nodes.
-    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-    const void* graph_table[3] = {nullptr, nullptr, nullptr};
+    // Captured [reset, (pass 0,) pass 1, pass 2] per pass mode, with the
+    // table address and grid sizes baked into the kernel nodes.
+    hipGraphExec_t exec[4] = {};
+    hipGraph_t graph[4] = {};
+    const void* graph_table[4] = {};
     // The call whose table the device copy holds: a repeat of the same
     // batch (same descriptors, outputs and pass mode) reuses it as is.
     std::vector<hx_image> last_imgs;
@@ -97,7 +98,7 @@ struct hx_pipeline {
     std::mutex batch_mu;  // guards context rotation (the server calls from
                           // its own thread)
     hipStream_t capture_stream = nullptr;
-    int batch_grid[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [pass mode][phase - 1]
+    int batch_grid[4][3] = {};  // [pass mode][phase]
     bool timing = false;
     int last_timed_ctx = -1;
 };

@@ -8,6 +8,10 @@
 //           only; both fold the tile's G^2 maximum into the image's slot;
 //   pass 2  one item = a run of rows (STORE: code -> mask) or one sweep tile
 //           (RECOMPUTE: every stage -> mask) of one image.
+// SPECULATE adds pass 0 (one item = one 16-row sampled band tile: blur +
+// Sobel -> a lower bound of the max), runs every stage in pass 1 (mask
+// against the bound's threshold, plus the list of pixels it set), and
+// re-decides only the listed pixels in pass 2 (one item = one pass-1 tile).
 // Pass 2 starts after pass 1 has finished (a kernel boundary), so every max
 // is final when it is read; no workgroup ever waits for another one.  Each
 // persistent wave strides over its pass's item list; the item lists live in
@@ -27,6 +31,9 @@ namespace hx {
 #ifndef HX_BATCH_TY
 #define HX_BATCH_TY 64
 #endif
+#ifndef HX_SPEC_WAVES
+#define HX_SPEC_WAVES 3
+#endif
 constexpr int kBC = HX_BATCH_C;    // columns per lane of the batch sweep
 constexpr int kBTY = HX_BATCH_TY;  // rows per sweep tile
 
@@ -39,16 +46,29 @@ __host__ __device__ inline int p2_rows(int64_t W) {
 }
 int batch_p2_rows(int64_t W) { return p2_rows(W); }
 
-size_t batch_table_bytes(int n, int64_t n1, int64_t n2) {
+size_t batch_table_bytes(int n, int64_t n1, int64_t n2, int64_t n0) {
     return sizeof(BatchHeader) + (size_t)n * sizeof(ImgArgs) +
-           (size_t)(n1 + n2) * sizeof(BatchItem);
+           (size_t)(n1 + n2 + n0) * sizeof(BatchItem);
 }
+
+int64_t batch_sample_items(int ks, int64_t H, int64_t W) {
+    const SweepGeom g{ks, kBC, kSampleRows};
+    return g.strips(W) * ((H + kSampleStride - 1) / kSampleStride);
+}
+
+int64_t batch_spec_entries() { return 64 * kBTY; }
+
+// The bound's threshold is scaled down by this factor so that it stays at
+// or below the true max's threshold even if the square root were not
+// monotone to the last ulp; it only lists a few more pixels.
+constexpr float kSpecSafety = 0.99999f;
 
 struct TableView {
     BatchHeader hdr;
     const ImgArgs* imgs;
     const BatchItem* items1;
     const BatchItem* items2;
+    const BatchItem* items0;
 };
 
 __device__ __forceinline__ TableView view(const uint8_t* __restrict__ table) {
@@ -57,6 +77,7 @@ __device__ __forceinline__ TableView view(const uint8_t* __restrict__ table) {
     v.imgs = reinterpret_cast<const ImgArgs*>(table + sizeof(BatchHeader));
     v.items1 = reinterpret_cast<const BatchItem*>(v.imgs + v.hdr.n_images);
     v.items2 = v.items1 + v.hdr.n_items1;
+    v.items0 = v.items2 + v.hdr.n_items2;
     return v;
 }
 
@@ -72,10 +93,34 @@ __device__ __forceinline__ int global_wave() {
                                           (int)(threadIdx.x >> 6));
 }
 
-template <int KS, int PASS>
-__global__ __launch_bounds__(256) void k_batch_p1(const uint8_t* __restrict__ table,
+// SPECULATE pass 0: G^2 on the sampled bands, folded into the slots.  Any
+// pixel's G^2 is at most the image's max, so the slot then holds a lower
+// bound of it (the exact max once pass 1 has run).
+template <int KS>
+__global__ __launch_bounds__(256) void k_batch_p0(const uint8_t* __restrict__ table,
                                                   Taps tp) {
-    constexpr int M1 = PASS == HX_PASS_STORE ? SM_STORE : SM_MAXONLY;
+    using S = SweepShape<KS, kBC, kSampleRows, SM_MAXONLY>;
+    const TableView tv = view(table);
+    const int nw = gridDim.x * 4;
+    for (int k = global_wave(); k < tv.hdr.n_items0; k += nw) {
+        const BatchItem it = tv.items0[k];
+        const ImgArgs a = tv.imgs[it.image];
+        const int nstrips = (a.W + S::OW - 1) / S::OW;
+        float gmax = 0.0f;
+        sweep_tile<KS, kBC, kSampleRows, SM_MAXONLY>(
+            a, tp, (it.local % nstrips) * S::OW, (it.local / nstrips) * kSampleStride, 0.0f,
+            gmax);
+        gmax = wave_max(gmax);
+        if (lane_id() == 0) atomic_max_g2(a.slot, gmax);
+    }
+}
+
+template <int KS, int PASS>
+__device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
+                                              const Taps& tp) {
+    constexpr int M1 = PASS == HX_PASS_STORE       ? SM_STORE
+                       : PASS == HX_PASS_SPECULATE ? SM_SPEC
+                                                   : SM_MAXONLY;
     using S = SweepShape<KS, kBC, kBTY, M1>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
@@ -84,11 +129,40 @@ __global__ __launch_bounds__(256) void k_batch_p1(const uint8_t* __restrict__ ta
         const ImgArgs a = tv.imgs[it.image];
         const int nstrips = (a.W + S::OW - 1) / S::OW;
         float gmax = 0.0f;
+        float thr2 = 0.0f;
+        SpecTile sp{nullptr, nullptr, 0u};
+        if constexpr (PASS == HX_PASS_SPECULATE) {
+            // The slot only grows within a batch (pass 0 and the other
+            // pass-1 tiles fold into it), so whatever value this reads is
+            // a lower bound of the final max.
+            const uint32_t lb2 =
+                __hip_atomic_load(a.slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            thr2 = thr2_from(lb2, tv.hdr.theta) * kSpecSafety;
+            const int64_t base = (int64_t)k * (64 * kBTY);
+            sp.code = tv.hdr.cand_code + base * kBC;
+            sp.row = tv.hdr.cand_row + base;
+        }
         sweep_tile<KS, kBC, kBTY, M1>(a, tp, (it.local % nstrips) * S::OW,
-                                      (it.local / nstrips) * kBTY, 0.0f, gmax);
+                                      (it.local / nstrips) * kBTY, thr2, gmax, &sp);
+        if constexpr (PASS == HX_PASS_SPECULATE)
+            as_global(tv.hdr.cand_n)[(int64_t)k * 64 + lane_id()] = sp.n;
         gmax = wave_max(gmax);
         if (lane_id() == 0) atomic_max_g2(a.slot, gmax);
     }
+}
+
+template <int KS, int PASS>
+__global__ __launch_bounds__(256) void k_batch_p1(const uint8_t* __restrict__ table,
+                                                  Taps tp) {
+    batch_p1_body<KS, PASS>(table, tp);
+}
+
+// SPECULATE's pass 1 holds a few more values than the others; capping it at
+// three waves per SIMD keeps the occupancy of the other pass-1 sweeps.
+template <int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SPEC_WAVES)))
+void k_batch_p1s(const uint8_t* __restrict__ table, Taps tp) {
+    batch_p1_body<KS, HX_PASS_SPECULATE>(table, tp);
 }
 
 template <int KS, int PASS>
@@ -113,6 +187,26 @@ __global__ __launch_bounds__(256) void k_batch_p2(const uint8_t* __restrict__ ta
                               ((a.mp % 4) == 0);
             for (int y = r0; y < r1; ++y)
                 for (int q = lane; q < wq; q += 64) threshold4(a, y, q * 4, thr2, mvec);
+        } else if constexpr (PASS == HX_PASS_SPECULATE) {
+            // Re-decide the pixels pass 1 listed for this tile, now that
+            // the max is final.
+            const int nstrips = (a.W + S::OW - 1) / S::OW;
+            const int x0 = (it.local % nstrips) * S::OW;
+            const int y0 = (it.local / nstrips) * kBTY;
+            const int cbase = x0 - S::HL + kBC * lane;
+            const uint32_t n = as_global(tv.hdr.cand_n)[(int64_t)k * 64 + lane];
+            const int64_t base = (int64_t)k * (64 * kBTY);
+            for (uint32_t j = 0; j < n; ++j) {
+                const int64_t idx = base + (int64_t)j * 64 + lane;
+                const gptr<const VecF<kBC>> q =
+                    (gptr<const VecF<kBC>>)(as_global(tv.hdr.cand_code) + idx * kBC);
+                const uint32_t rw = (uint32_t)as_global(tv.hdr.cand_row)[idx];
+                const int y = y0 + (int)(rw >> 4);
+                const gptr<uint8_t> rp = as_global(a.mask) + (int64_t)y * a.mp + cbase;
+#pragma unroll
+                for (int e = 0; e < kBC; ++e)
+                    if ((rw >> e) & 1u) rp[e] = q->v[e] > thr2 ? 1 : 0;
+            }
         } else {
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             float unused = 0.0f;
@@ -132,13 +226,19 @@ hipError_t launch_batch_reset(const void* d_table, uint32_t* slots, int max_imag
 }
 
 static const void* batch_kernel_ptr(int ks, int pass, int phase) {
-#define HX_B(K)                                                                        \
-    if (ks == K) {                                                                     \
-        if (phase == 1)                                                                \
-            return pass == HX_PASS_STORE ? (const void*)k_batch_p1<K, HX_PASS_STORE>      \
-                                         : (const void*)k_batch_p1<K, HX_PASS_RECOMPUTE>; \
-        return pass == HX_PASS_STORE ? (const void*)k_batch_p2<K, HX_PASS_STORE>          \
-                                     : (const void*)k_batch_p2<K, HX_PASS_RECOMPUTE>;      \
+#define HX_B(K)                                                                      \
+    if (ks == K) {                                                                   \
+        if (phase == 0)                                                              \
+            return pass == HX_PASS_SPECULATE ? (const void*)k_batch_p0<K> : nullptr; \
+        if (pass == HX_PASS_STORE)                                                   \
+            return phase == 1 ? (const void*)k_batch_p1<K, HX_PASS_STORE>            \
+                              : (const void*)k_batch_p2<K, HX_PASS_STORE>;           \
+        if (pass == HX_PASS_RECOMPUTE)                                               \
+            return phase == 1 ? (const void*)k_batch_p1<K, HX_PASS_RECOMPUTE>        \
+                              : (const void*)k_batch_p2<K, HX_PASS_RECOMPUTE>;       \
+        if (pass == HX_PASS_SPECULATE)                                               \
+            return phase == 1 ? (const void*)k_batch_p1s<K>                          \
+                              : (const void*)k_batch_p2<K, HX_PASS_SPECULATE>;       \
     }
     HX_B(3) HX_B(5) HX_B(7)
 #undef HX_B

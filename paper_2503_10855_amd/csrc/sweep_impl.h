@@ -50,8 +50,9 @@ struct SweepShape {
 #endif
     static constexpr int PF = HX_SWEEP_PF;                 // prefetch rows
     static constexpr bool NEED_L =
-        MODE == SM_STORE || MODE == SM_MASK || MODE == SM_BGL;
-    static constexpr bool NEED_Z = MODE == SM_STORE || MODE == SM_MASK;
+        MODE == SM_STORE || MODE == SM_MASK || MODE == SM_SPEC || MODE == SM_BGL;
+    static constexpr bool NEED_Z =
+        MODE == SM_STORE || MODE == SM_MASK || MODE == SM_SPEC;
     static constexpr bool DO_MAX = MODE != SM_MASK;
     static_assert(TY % P == 0, "tile height must be a multiple of the ring period");
     static_assert(KS <= P, "the horizontal-blur ring must hold k rows");
@@ -126,12 +127,13 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 
 // Run one tile: output columns [x0, x0+OW) x rows [y0, y0+TY), clipped to
 // the image.  BX / BY: the tile's input window crosses a column / row
-// border of the image.  thr2 is used by SM_MASK only.  gmax accumulates
-// G^2 over real image pixels of the tile (per lane; the caller reduces).
+// border of the image.  thr2 is used by SM_MASK and SM_SPEC only.  gmax
+// accumulates G^2 over real image pixels of the tile (per lane; the caller
+// reduces).  sp: SM_SPEC's list of the pixels it set.
 template <int KS, int C, int TY, int MODE, bool BX, bool BY>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, float thr2,
-                                           float& gmax) {
+                                           float& gmax, SpecTile* sp) {
     using S = SweepShape<KS, C, TY, MODE>;
     constexpr int R = S::R, HX = S::HX, HL = S::HL, SW = S::SW, OW = S::OW;
     constexpr int NS = S::NS, NP = S::NP, P = S::P, PF = S::PF;
@@ -355,6 +357,27 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                     for (int e = 0; e < C; ++e)
                                         if (ecol[e]) rp[e] = (uint8_t)m[e];
                                 }
+                                if constexpr (MODE == SM_SPEC) {
+                                    // List this lane's row if it set a bit:
+                                    // its C values of G^2, and the row with
+                                    // the set columns as low bits.
+                                    static_assert(C <= 4, "four set-bits per entry");
+                                    uint32_t bits = 0;
+#pragma unroll
+                                    for (int e = 0; e < C; ++e)
+                                        bits |= ((m[e] != 0u) & (BX ? ecol[e] : lane_out))
+                                                    ? (1u << e) : 0u;
+                                    if (bits) {
+                                        const int64_t idx = (int64_t)sp->n * 64 + lane;
+                                        const gptr<VecF<C>> q =
+                                            (gptr<VecF<C>>)(as_global(sp->code) + idx * C);
+#pragma unroll
+                                        for (int e = 0; e < C; ++e) q->v[e] = g2d[e];
+                                        as_global(sp->row)[idx] =
+                                            (int32_t)(((uint32_t)(vz - y0) << 4) | bits);
+                                        sp->n += 1;
+                                    }
+                                }
                             }
                         }
                     }
@@ -387,19 +410,19 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
 template <int KS, int C, int TY, int MODE>
 __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, float thr2,
-                                           float& gmax) {
+                                           float& gmax, SpecTile* sp = nullptr) {
     using S = SweepShape<KS, C, TY, MODE>;
     const int xs = x0 - S::HL;
     const bool bx = (xs < 0) | (xs + S::SW > a.W);
     const bool by = (y0 - S::HX < 0) | (y0 + TY + S::HX > a.H);
     if (!bx & !by)
-        sweep_body<KS, C, TY, MODE, false, false>(a, tp, x0, y0, thr2, gmax);
+        sweep_body<KS, C, TY, MODE, false, false>(a, tp, x0, y0, thr2, gmax, sp);
     else if (!bx)
-        sweep_body<KS, C, TY, MODE, false, true>(a, tp, x0, y0, thr2, gmax);
+        sweep_body<KS, C, TY, MODE, false, true>(a, tp, x0, y0, thr2, gmax, sp);
     else if (!by)
-        sweep_body<KS, C, TY, MODE, true, false>(a, tp, x0, y0, thr2, gmax);
+        sweep_body<KS, C, TY, MODE, true, false>(a, tp, x0, y0, thr2, gmax, sp);
     else
-        sweep_body<KS, C, TY, MODE, true, true>(a, tp, x0, y0, thr2, gmax);
+        sweep_body<KS, C, TY, MODE, true, true>(a, tp, x0, y0, thr2, gmax, sp);
 }
 
 }  // namespace hx

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhx.so")
 
 HX_OK, HX_E_INVALID, HX_E_NOMEM, HX_E_HIP, HX_E_UNSUPPORTED, HX_E_BUSY, \
     HX_E_PENDING, HX_E_NOT_FOUND = range(8)
-PASS_AUTO, PASS_STORE, PASS_RECOMPUTE = 0, 1, 2
+PASS_AUTO, PASS_STORE, PASS_RECOMPUTE, PASS_SPECULATE = 0, 1, 2, 3
 REDUCE_TREE, REDUCE_TWO_LEVEL, REDUCE_SEQUENTIAL = 0, 1, 2
 
 
@@ -192,9 +192,10 @@ class Pipeline:
         _check(_lib.hx_pipeline_set_timing(self._h, 1 if enable else 0), "set_timing")
 
     def last_timing(self):
-        """(reset, pass 1, pass 2) durations in ms of the last batched call
-        made in timing mode (waits for it)."""
-        ms = (ctypes.c_float * 3)()
+        """(reset, pass 1, pass 2, pass 0) durations in ms of the last
+        batched call made in timing mode (waits for it); pass 0 runs under
+        SPECULATE only and is 0 otherwise."""
+        ms = (ctypes.c_float * 4)()
         _check(_lib.hx_pipeline_last_timing(self._h, ms), "last_timing")
         return tuple(ms)
 

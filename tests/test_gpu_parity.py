@@ -57,6 +57,7 @@ SCHEDULES = [
     (64, 16, 4, 1, 0), (64, 128, 4, 1, 0), (128, 32, 4, 1, 0),
     (256, 16, 4, 1, 0), (256, 64, 4, 1, 0), (256, 128, 4, 1, 0),
     (64, 64, 4, 2, 0), (128, 16, 4, 2, 0), (256, 32, 4, 2, 0), (256, 64, 4, 2, 0),
+    (256, 64, 4, 3, 0),
     (64, 16, 1, 1, 1), (32, 32, 1, 1, 2),
 ]
 
@@ -106,7 +107,7 @@ def test_every_schedule_bit_identical(hx, shape, ks, sigma):
 
 
 @pytest.mark.parametrize("ks,sigma", [(5, 1.0), (7, 1.5)])
-@pytest.mark.parametrize("pass_mode", [1, 2])
+@pytest.mark.parametrize("pass_mode", [1, 2, 3])
 def test_batched_equals_per_image(hx, ks, sigma, pass_mode):
     sizes = [(1, 1), (64, 64), (5, 900), (333, 17), (256, 256), (130, 517),
              (1080, 1920), (2, 3), (700, 65), (64, 249)]
@@ -131,6 +132,50 @@ def test_batched_equals_per_image(hx, ks, sigma, pass_mode):
         assert float(dmax[i].cpu()) == M1
         assert abs(M1 - o["M"]) <= 1e-5 * o["M"]
         assert_mask(m, o, f"batched {sizes[i]}")
+
+
+def weak_bound_images():
+    """Images on which the sampled bands of SPECULATE (16 rows in every 128)
+    see a poor lower bound of the max, or none at all, so pass 1 lists many
+    or most pixels: the strongest edge sits between the bands, or the bands
+    are flat (bound 0: every pixel with Z = 1 and G > 0 is listed)."""
+    out = []
+    a = synth.image(300, 700, 26, 0) * 0.2
+    a[60:90, 200:260] += 5.0            # the strongest edge, rows 16..127
+    out.append(a.astype(np.float32))
+    b = synth.image(290, 513, 26, 1)
+    for y0 in range(0, 290, 128):       # flat over each band and its halo
+        b[max(0, y0 - 4):y0 + 20] = 0.3
+    out.append(b.astype(np.float32))
+    rng = np.random.default_rng(np.random.SeedSequence([26, 2]))
+    out.append(rng.uniform(0, 1, (200, 333)).astype(np.float32))  # pure noise
+    c = np.full((140, 260), 0.5, np.float32)
+    c[:, 130:] = 0.25                   # one vertical step through every band
+    out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("ks,sigma", [(5, 1.0), (3, 0.8), (7, 1.5)])
+def test_speculate_with_weak_bound(hx, ks, sigma):
+    """SPECULATE is exact whatever its bound: per image and batched, its
+    masks equal RECOMPUTE's bit for bit and the oracle's."""
+    imgs = weak_bound_images()
+    srcs = [dev(a) for a in imgs]
+    res = {}
+    for pm in (2, 3):
+        with hx.Pipeline(ksize=ks, sigma=sigma, theta=THETA, pass_mode=pm) as p:
+            dmax = torch.zeros(len(imgs), device="cuda")
+            print(f"weak bound ks={ks} pass={pm}: batched", flush=True)
+            masks = p.edge_detect_batched(srcs, dmax=dmax)
+            p.sync()
+            one = [p.edge_detect(s).cpu().numpy() for s in srcs]
+            torch.cuda.synchronize()
+            res[pm] = ([m.cpu().numpy() for m in masks], one, dmax.cpu().numpy())
+    for i, a in enumerate(imgs):
+        assert np.array_equal(res[3][0][i], res[2][0][i]), i
+        assert np.array_equal(res[3][1][i], res[2][0][i]), i
+        assert res[3][2][i] == res[2][2][i], i
+        assert_mask(res[3][0][i], ora(a, ks, sigma), f"weak bound {i} {a.shape}")
 
 
 @pytest.mark.skip(reason="the single-kernel batched variant, in which pass-2 "
@@ -158,7 +203,7 @@ def test_batched_graph_replay_with_changing_batches(hx):
 
 
 @pytest.mark.parametrize("sched", [(256, 64, 4, 1, 0), (64, 16, 1, 1, 0),
-                                   (128, 32, 4, 2, 0)])
+                                   (128, 32, 4, 2, 0), (256, 64, 4, 3, 0)])
 def test_pitch_and_misalignment(hx, sched):
     """Padded row pitches and bases that are not 16-byte aligned take the
     scalar load/store paths; results must not change and bytes outside the
@@ -222,6 +267,10 @@ def test_abi_rejects_bad_arguments(hx):
         bad = hx.Schedule(48, 16, 1, 1, 0)
         assert lib.hx_pipeline_set_schedule(p.handle, ctypes.byref(bad)) == hx.HX_E_INVALID
         bad = hx.Schedule(256, 64, 4, 1, 2)
+        assert lib.hx_pipeline_set_schedule(p.handle, ctypes.byref(bad)) == hx.HX_E_INVALID
+        bad = hx.Schedule(128, 64, 4, 3, 0)  # SPECULATE needs the 256x64 tile
+        assert lib.hx_pipeline_set_schedule(p.handle, ctypes.byref(bad)) == hx.HX_E_INVALID
+        bad = hx.Schedule(256, 64, 4, 4, 0)
         assert lib.hx_pipeline_set_schedule(p.handle, ctypes.byref(bad)) == hx.HX_E_INVALID
         torch.cuda.synchronize()
         assert int((mask != 5).sum()) == 0  # nothing was enqueued
