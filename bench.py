@@ -32,9 +32,11 @@ PATH_BYTES_PER_PX = 5.0    # input read once + mask written once
 # SPECULATE's pass 1 reads the input and writes the mask; its pass 2
 # touches only the listed pixels.
 KERNEL_BYTES_PER_PX = {1: {1: 4.0, 2: 1.0}, 2: {1: 4.0, 2: 5.0}, 3: {1: 5.0, 2: 0.0}}
+BATCH_DEFAULT_PASS = 3    # the library's pass structure for batched calls
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_64x1080p.json")
 SWEEP_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in
-                 ("sweep_impl.h", "hx_device.h", "k_batch.hip", "thresh_impl.h")]
+                 ("sweep_impl.h", "hx_device.h", "hx_kernels.h", "k_batch.hip",
+                  "thresh_impl.h")]
 
 
 def workloads():
@@ -234,11 +236,12 @@ def main():
         p.set_schedule()
 
     # The dominant kernel is the longer of the two passes.
-    pm = args.pass_mode or 2
+    pm = args.pass_mode or BATCH_DEFAULT_PASS
     dom = 1 if ms_p1 >= ms_p2 else 2
     ms_dom = ms_p1 if dom == 1 else ms_p2
     bpp = KERNEL_BYTES_PER_PX[pm][dom]
-    kname = f"k_batch_p{dom}<{wl.ksize}, {pm}>"
+    kname = (f"k_batch_p1s<{wl.ksize}>" if (pm, dom) == (3, 1)
+             else f"k_batch_p{dom}<{wl.ksize}, {pm}>")
     achieved = bpp * pixels / (ms_dom * 1e-3) / 1e9
     traffic = measured_traffic(kname, pixels)
     line = {
@@ -339,10 +342,13 @@ def run_serve(args, hx):
             t0 = srv.now() + 0.05
             i = done = 0
             next_report = 1.0
+            last_done, last_change = 0, srv.now()
             while done < n:
                 now = srv.now()
                 while i < n and t0 + arrivals[i] <= now:
-                    t = srv.submit(views[i], arrival=t0 + arrivals[i])
+                    t = srv.try_submit(views[i], arrival=t0 + arrivals[i])
+                    if t is None:
+                        break  # pinned pool full until finished requests are polled
                     pending[t] = (i, np.empty(views[i].shape, np.uint8))
                     i += 1
                 for t in list(pending):
@@ -358,6 +364,11 @@ def run_serve(args, hx):
                     print(f"serve: {now - t0:.1f} s, {done} done, {len(pending)} pending",
                           file=sys.stderr, flush=True)
                     next_report += 1.0
+                if done != last_done:
+                    last_done, last_change = done, now
+                elif now - last_change > 30.0:
+                    raise RuntimeError(f"serve: no request finished for 30 s "
+                                       f"({done} done, {len(pending)} pending)")
                 if i < n and not pending:
                     time.sleep(max(0.0, min(2e-4, t0 + arrivals[i] - srv.now())))
             t_end = srv.now()

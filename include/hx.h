@@ -67,7 +67,7 @@ typedef struct hx_server hx_server;
  *  RECOMPUTE:  pass 1 computes blur and Sobel only, for the max; pass 2
  *              recomputes every stage and writes the mask directly.
  *  SPECULATE:  pass 0 computes G^2 on sampled row bands (16 rows in every
- *              128) for a lower bound m <= max G^2 of each image; pass 1
+ *              256) for a lower bound m <= max G^2 of each image; pass 1
  *              computes every stage once, writes the mask against the
  *              threshold of m (a pixel it leaves at 0 is 0 under the true
  *              max too) and lists the pixels it set, with their G^2;
@@ -80,9 +80,10 @@ enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2,
 /* Shape of the max reduction (the paper's reduction_tree schedule and its
  * warp-primitive refinement, Use and Impact of Schedules):
  *  TREE:        per-lane max, wave64 shuffle tree, one atomic per wave.
- *  TWO_LEVEL:   per-thread partial maxima written out, then one thread per
- *               image combines them serially (a tree without wave
- *               primitives).
+ *  TWO_LEVEL:   the reduction_tree schedule: 4096 threads each fold a
+ *               strided chunk of the stored G^2 plane from the identity,
+ *               then one thread combines their 4096 partial maxima
+ *               serially (a two-level tree without wave primitives).
  *  SEQUENTIAL:  one thread per image scans every G value (no tree).
  * TWO_LEVEL and SEQUENTIAL exist for the ablation; they need
  * fusion_depth 1. */
@@ -228,10 +229,12 @@ hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp,
                           void* d_arena, size_t arena_bytes, hx_server** out);
 
 /* Enqueue one request.  h_src: host fp32 image, h rows of w values, row
- * pitch `pitch` elements; it is copied before the call returns.
- * arrival_s: the request's scheduled arrival time on the server's clock
- * (hx_serve_now), used for latency.  HX_E_BUSY if the request alone can
- * never fit the budget. */
+ * pitch `pitch` elements; it is copied (into the server's pinned pool)
+ * before the call returns.  arrival_s: the request's scheduled arrival time
+ * on the server's clock (hx_serve_now), used for latency.  Never blocks:
+ * HX_E_PENDING if the pinned pool has no room right now (it fills with
+ * finished requests until they are collected: poll, then submit again),
+ * HX_E_BUSY if the request alone can never fit the budget. */
 hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h,
                           int64_t w, int64_t pitch, double arrival_s,
                           uint64_t* ticket);

@@ -228,9 +228,7 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
     b.B = (float*)p->bufB.ptr;
     b.L = (float*)p->bufL.ptr;
     if (s.reduce_mode == HX_REDUCE_TWO_LEVEL) {
-        const int64_t tiles =
-            ((a.W + s.tile_w - 1) / s.tile_w) * (int64_t)((a.H + s.tile_h - 1) / s.tile_h);
-        HX_TRY(p->bufPart.ensure((size_t)tiles * 256 * sizeof(float)));
+        HX_TRY(p->bufPart.ensure((size_t)kTreeThreads * sizeof(float)));
         b.partial = (float*)p->bufPart.ptr;
     }
     HX_TRY(launch_blur(a, b, p->taps, ks, s.tile_w, s.tile_h, stream));
@@ -244,7 +242,8 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
 // ------------------------------------------------------------- batched --
 static hx_status ctx_init(hx_pipeline* p, BatchContext& c) {
     if (c.ready) return HX_OK;
-    HX_TRY(hipMalloc(&c.slots, sizeof(uint32_t) * p->prm.max_images));
+    // Max slots, then (SPECULATE) as many bound slots.
+    HX_TRY(hipMalloc(&c.slots, 2 * sizeof(uint32_t) * p->prm.max_images));
     HX_TRY(hipEventCreateWithFlags(&c.ev_done, hipEventDisableTiming));
     for (auto& e : c.ev_t) HX_TRY(hipEventCreate(&e));
     c.ready = true;
@@ -404,7 +403,7 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
         const size_t entries = (size_t)n1 * batch_spec_entries();
         HX_TRY(c.cand_code.ensure(entries * geo.c * sizeof(float)));
         HX_TRY(c.cand_row.ensure(entries * sizeof(int32_t)));
-        HX_TRY(c.cand_n.ensure((size_t)n1 * 64 * sizeof(uint32_t)));
+        HX_TRY(c.cand_n.ensure((size_t)n1 * sizeof(uint32_t)));
     }
     const size_t bytes = batch_table_bytes(n, n1, n2, n0);
     HX_TRY(c.table.ensure(bytes));
@@ -429,6 +428,7 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
         hdr.cand_code = (float*)c.cand_code.ptr;
         hdr.cand_row = (int32_t*)c.cand_row.ptr;
         hdr.cand_n = (uint32_t*)c.cand_n.ptr;
+        hdr.bound = c.slots + p->prm.max_images;
     }
     std::memcpy(h, &hdr, sizeof hdr);
     ImgArgs* ia = (ImgArgs*)(h + sizeof(BatchHeader));
@@ -652,10 +652,7 @@ hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs, int32_t n
         }
         return HX_OK;
     }
-    // Batches default to RECOMPUTE: two reads of the input but no code
-    // round trip, measured faster on the 64x1080p batch (both passes run
-    // near the copy bandwidth).
-    int pass = HX_PASS_RECOMPUTE;
+    int pass = kBatchPass;
     if (p->prm.pass_mode) pass = p->prm.pass_mode;
     if (p->forced && p->forced_sched.fusion_depth == 4) pass = p->forced_sched.pass_mode;
     return run_batched(p, imgs, n, d_max, pass, stream);

@@ -20,11 +20,11 @@ enum SweepMode : int {
                      // the list of pixels it set (SpecTile), and the max
 };
 
-// Where one SM_SPEC tile lists the pixels whose mask bit it set.  Entry
-// (j, lane) -- the lane's j-th listed row -- sits at index j * 64 + lane:
-// code[] holds G^2 of the lane's C pixels of that row, and row[] the row's
-// offset from the tile top times 16 plus a bit per column that was set.
-// n counts the entries of the calling lane.
+// Where one SM_SPEC tile lists the pixels whose mask bit it set.  One
+// entry per (row, lane) that set a bit, packed in row then lane order:
+// code[] holds G^2 of the lane's C pixels of that row, and row[] packs
+// (row offset from the tile top) << 10 | lane << 4 | a bit per column
+// that was set.  n counts the tile's entries (the same in every lane).
 struct SpecTile {
     float* code;     // C floats per entry
     int32_t* row;
@@ -79,9 +79,11 @@ struct StageBufs {
     float* L;
     float* G2;
     uint8_t* Z;      // pitch op bytes
-    float* partial;  // TWO_LEVEL: per-thread partial maxima
+    float* partial;  // TWO_LEVEL: kTreeThreads partial maxima
     int64_t op;
 };
+// Threads of the first level of the TWO_LEVEL max reduction.
+constexpr int kTreeThreads = 4096;
 hipError_t launch_blur(const ImgArgs& a, const StageBufs& b, const Taps& t,
                        int ks, int tw, int th, hipStream_t s);
 hipError_t launch_laplacian(const ImgArgs& a, const StageBufs& b, int tw,
@@ -120,27 +122,29 @@ struct BatchHeader {
     int32_t pad[2];
     // SPECULATE: the listed pixels of pass-1 item k occupy entries
     // [k * 64 * TY, (k + 1) * 64 * TY) of cand_code / cand_row, and
-    // cand_n[k * 64 + lane] counts the lane's entries.
+    // cand_n[k] counts them.
     float* cand_code;
     int32_t* cand_row;
     uint32_t* cand_n;
-    void* pad2;
+    // SPECULATE: per-image lower bounds of max G^2 (bits), written by pass
+    // 0 and only read by pass 1, whose own maxima go to the images' slots.
+    uint32_t* bound;
 };
 
 size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2,
                          int64_t n_items0);
-// SPECULATE: pass-0 band geometry (16 sampled rows at the top of every 128)
+// SPECULATE: pass-0 band geometry (16 sampled rows at the top of every 256)
 // and the listed-pixel capacity of one pass-1 item, in entries.
 constexpr int kSampleRows = 16;
-constexpr int kSampleStride = 128;
+constexpr int kSampleStride = 256;
 int64_t batch_sample_items(int ks, int64_t H, int64_t W);
 int64_t batch_spec_entries();  // 64 * TY
 int batch_sweep_c();   // columns per lane of the batch sweep
 int batch_sweep_ty();  // rows per batch sweep tile
 // Rows per pass-2 item of the STORE threshold for width W.
 int batch_p2_rows(int64_t W);
-// Zero the first n (read from the table) max slots; grid sized for
-// max_images.
+// Zero the first n (read from the table) max slots, and as many bound
+// slots when the table has them; grid sized for max_images.
 hipError_t launch_batch_reset(const void* d_table, uint32_t* slots,
                               int max_images, hipStream_t s);
 // One pass (phase 0, 1 or 2) over the table's item list on `grid`

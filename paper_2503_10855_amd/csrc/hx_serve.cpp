@@ -120,7 +120,6 @@ struct hx_server {
 
     std::mutex mu;
     std::condition_variable cv;        // wakes the scheduler
-    std::condition_variable host_cv;   // wakes submitters waiting for pool room
     std::unordered_map<uint64_t, std::unique_ptr<hx::Request>> reqs;
     std::deque<hx::Request*> queued, admitted;
     std::deque<std::pair<int, std::vector<hx::Request*>>> finished;  // (stream, reqs)
@@ -191,7 +190,7 @@ void launch_batch(hx_server* s, std::unique_lock<std::mutex>& lk, int k,
         e = hipMemcpyAsync(const_cast<float*>(imgs[i].src), s->host + batch[i]->host_off,
                            batch[i]->in_bytes(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        rc = run_batched(s->p, imgs.data(), (int32_t)imgs.size(), nullptr, HX_PASS_RECOMPUTE, st);
+        rc = run_batched(s->p, imgs.data(), (int32_t)imgs.size(), nullptr, kBatchPass, st);
     for (size_t i = 0; i < batch.size() && e == hipSuccess && rc == HX_OK; ++i)
         e = hipMemcpyAsync(s->host + batch[i]->host_off + align_up(batch[i]->in_bytes()),
                            imgs[i].mask, batch[i]->mask_bytes(), hipMemcpyDeviceToHost, st);
@@ -337,10 +336,11 @@ hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h, int64_t w
     if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
     if (dev_need > s->dev_alloc->size() || r->host_bytes > s->host_alloc->size())
         return fail(HX_E_BUSY, "request of %zu bytes can never fit the budget", dev_need);
-    while (!s->host_alloc->alloc(r->host_bytes, &r->host_off)) {
-        if (s->stop) return fail(HX_E_INVALID, "server is shutting down");
-        s->host_cv.wait(lk);
-    }
+    if (s->stop) return fail(HX_E_INVALID, "server is shutting down");
+    // Never wait here for pool room: it is freed only by hx_serve_poll,
+    // which a single-threaded caller could then never reach.
+    if (!s->host_alloc->alloc(r->host_bytes, &r->host_off))
+        return fail(HX_E_PENDING, "pinned pool full: poll finished requests, then retry");
     r->id = s->next_id++;
     Request* rp = r.get();
     s->reqs.emplace(rp->id, std::move(r));
@@ -383,7 +383,6 @@ hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
     if (service_s) *service_s = r->done_t - r->launch_t;
     s->host_alloc->release(r->host_off, r->host_bytes);
     s->reqs.erase(it);
-    s->host_cv.notify_all();
     return HX_OK;
 }
 
@@ -405,7 +404,6 @@ hx_status hx_serve_destroy(hx_server* s) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
         s->cv.notify_all();
-        s->host_cv.notify_all();
     }
     if (s->sched.joinable()) s->sched.join();
     hx_status st = s->sticky;

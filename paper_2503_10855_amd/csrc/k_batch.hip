@@ -31,8 +31,8 @@ namespace hx {
 #ifndef HX_BATCH_TY
 #define HX_BATCH_TY 64
 #endif
-#ifndef HX_SPEC_WAVES
-#define HX_SPEC_WAVES 3
+#ifndef HX_SWEEP_WAVES
+#define HX_SWEEP_WAVES 3
 #endif
 constexpr int kBC = HX_BATCH_C;    // columns per lane of the batch sweep
 constexpr int kBTY = HX_BATCH_TY;  // rows per sweep tile
@@ -82,9 +82,13 @@ __device__ __forceinline__ TableView view(const uint8_t* __restrict__ table) {
 }
 
 __global__ void k_batch_reset(const uint8_t* __restrict__ table, uint32_t* slots) {
-    const int n = reinterpret_cast<const BatchHeader*>(table)->n_images;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    const BatchHeader* h = reinterpret_cast<const BatchHeader*>(table);
+    const int n = h->n_images;
+    uint32_t* bound = h->bound;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         slots[i] = 0;
+        if (bound) bound[i] = 0;
+    }
 }
 
 // Index of this wave among all waves of the grid (XCD-contiguous).
@@ -93,12 +97,12 @@ __device__ __forceinline__ int global_wave() {
                                           (int)(threadIdx.x >> 6));
 }
 
-// SPECULATE pass 0: G^2 on the sampled bands, folded into the slots.  Any
-// pixel's G^2 is at most the image's max, so the slot then holds a lower
-// bound of it (the exact max once pass 1 has run).
+// SPECULATE pass 0: G^2 on the sampled bands, folded into the images'
+// bound slots.  Any pixel's G^2 is at most the image's max, so each then
+// holds a lower bound of it.
 template <int KS>
-__global__ __launch_bounds__(256) void k_batch_p0(const uint8_t* __restrict__ table,
-                                                  Taps tp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
     using S = SweepShape<KS, kBC, kSampleRows, SM_MAXONLY>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(256) void k_batch_p0(const uint8_t* __restrict__ ta
             a, tp, (it.local % nstrips) * S::OW, (it.local / nstrips) * kSampleStride, 0.0f,
             gmax);
         gmax = wave_max(gmax);
-        if (lane_id() == 0) atomic_max_g2(a.slot, gmax);
+        if (lane_id() == 0) atomic_max_g2(tv.hdr.bound + it.image, gmax);
     }
 }
 
@@ -132,11 +136,11 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
         float thr2 = 0.0f;
         SpecTile sp{nullptr, nullptr, 0u};
         if constexpr (PASS == HX_PASS_SPECULATE) {
-            // The slot only grows within a batch (pass 0 and the other
-            // pass-1 tiles fold into it), so whatever value this reads is
-            // a lower bound of the final max.
-            const uint32_t lb2 =
-                __hip_atomic_load(a.slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // Pass 0 finished before this kernel began, and nothing writes
+            // the bounds meanwhile.  (Reading the image's slot, which the
+            // other tiles keep raising, measured much slower: each read
+            // waits behind this wave's own atomic on the same address.)
+            const uint32_t lb2 = as_global(tv.hdr.bound)[it.image];
             thr2 = thr2_from(lb2, tv.hdr.theta) * kSpecSafety;
             const int64_t base = (int64_t)k * (64 * kBTY);
             sp.code = tv.hdr.cand_code + base * kBC;
@@ -145,29 +149,30 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
         sweep_tile<KS, kBC, kBTY, M1>(a, tp, (it.local % nstrips) * S::OW,
                                       (it.local / nstrips) * kBTY, thr2, gmax, &sp);
         if constexpr (PASS == HX_PASS_SPECULATE)
-            as_global(tv.hdr.cand_n)[(int64_t)k * 64 + lane_id()] = sp.n;
+            if (lane_id() == 0) as_global(tv.hdr.cand_n)[k] = sp.n;
         gmax = wave_max(gmax);
         if (lane_id() == 0) atomic_max_g2(a.slot, gmax);
     }
 }
 
+// The sweep kernels are capped at three waves per SIMD (at most 168
+// registers): left alone, the scheduler keeps more rows in flight and
+// the kernels fall to two waves per SIMD, which measured slower.
 template <int KS, int PASS>
-__global__ __launch_bounds__(256) void k_batch_p1(const uint8_t* __restrict__ table,
-                                                  Taps tp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+void k_batch_p1(const uint8_t* __restrict__ table, Taps tp) {
     batch_p1_body<KS, PASS>(table, tp);
 }
 
-// SPECULATE's pass 1 holds a few more values than the others; capping it at
-// three waves per SIMD keeps the occupancy of the other pass-1 sweeps.
 template <int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SPEC_WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p1s(const uint8_t* __restrict__ table, Taps tp) {
     batch_p1_body<KS, HX_PASS_SPECULATE>(table, tp);
 }
 
 template <int KS, int PASS>
-__global__ __launch_bounds__(256) void k_batch_p2(const uint8_t* __restrict__ table,
-                                                  Taps tp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
     using S = SweepShape<KS, kBC, kBTY, SM_MASK>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
@@ -193,15 +198,15 @@ __global__ __launch_bounds__(256) void k_batch_p2(const uint8_t* __restrict__ ta
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             const int x0 = (it.local % nstrips) * S::OW;
             const int y0 = (it.local / nstrips) * kBTY;
-            const int cbase = x0 - S::HL + kBC * lane;
-            const uint32_t n = as_global(tv.hdr.cand_n)[(int64_t)k * 64 + lane];
+            const int n = (int)as_global(tv.hdr.cand_n)[k];
             const int64_t base = (int64_t)k * (64 * kBTY);
-            for (uint32_t j = 0; j < n; ++j) {
-                const int64_t idx = base + (int64_t)j * 64 + lane;
+            for (int t = lane; t < n; t += 64) {
+                const int64_t idx = base + t;
                 const gptr<const VecF<kBC>> q =
                     (gptr<const VecF<kBC>>)(as_global(tv.hdr.cand_code) + idx * kBC);
                 const uint32_t rw = (uint32_t)as_global(tv.hdr.cand_row)[idx];
-                const int y = y0 + (int)(rw >> 4);
+                const int y = y0 + (int)(rw >> 10);
+                const int cbase = x0 - S::HL + kBC * (int)((rw >> 4) & 63u);
                 const gptr<uint8_t> rp = as_global(a.mask) + (int64_t)y * a.mp + cbase;
 #pragma unroll
                 for (int e = 0; e < kBC; ++e)

@@ -121,7 +121,8 @@ __device__ __forceinline__ float g2_at(const float* B, int64_t op, int y,
     return sobel_g2(dxr[0], dxr[1], dxr[2], syr[0], syr[2]);
 }
 
-// reduce: 0 tree (wave shuffle + atomic), 1 per-thread partials.
+// reduce: HX_REDUCE_TREE folds the max in here (wave shuffle + atomic);
+// the other modes reduce the stored G^2 plane afterwards.
 __global__ __launch_bounds__(256) void k_sobel(ImgArgs a, StageBufs b,
                                               TileMap m, int reduce) {
     float mx = 0.0f;
@@ -135,13 +136,25 @@ __global__ __launch_bounds__(256) void k_sobel(ImgArgs a, StageBufs b,
     if (reduce == HX_REDUCE_TREE) {
         mx = wave_max(mx);
         if (lane_id() == 0) atomic_max_g2(a.slot, mx);
-    } else if (reduce == HX_REDUCE_TWO_LEVEL) {
-        b.partial[(int64_t)blockIdx.x * 256 + threadIdx.x] = mx;
     }
 }
 
-// Final level of the TWO_LEVEL tree: one thread combines every partial,
-// in order (the paper's fission into a parallel and a serial fork).
+// First level of the TWO_LEVEL tree (the reduction_tree schedule: chunk the
+// reduction over kTreeThreads threads, each starting from the identity):
+// thread t folds the G^2 values t, t + N, t + 2N, ... of the plane, in
+// order, into partial[t].
+__global__ __launch_bounds__(256) void k_chunk_max(ImgArgs a, const float* G2, int64_t op,
+                                                  float* partial) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)a.H * op;
+    float mx = 0.0f;
+    for (int64_t i = t; i < n; i += kTreeThreads)
+        if (i % op < a.W) mx = __builtin_fmaxf(mx, G2[i]);
+    partial[t] = mx;
+}
+
+// Second level: one thread combines the partials in order (the fission of
+// the chunked loop into a parallel and a serial fork).
 __global__ void k_combine_partials(ImgArgs a, const float* partial, int64_t n) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     float mx = 0.0f;
@@ -271,8 +284,12 @@ hipError_t launch_sobel_max(const ImgArgs& a, const StageBufs& b, int tw,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (reduce_mode == HX_REDUCE_TWO_LEVEL) {
+        hipLaunchKernelGGL(k_chunk_max, dim3(kTreeThreads / 256), dim3(256), 0, s, a,
+                           (const float*)b.G2, b.op, b.partial);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_combine_partials, dim3(1), dim3(64), 0, s, a,
-                           (const float*)b.partial, (int64_t)grid_of(m) * 256);
+                           (const float*)b.partial, (int64_t)kTreeThreads);
         e = hipGetLastError();
     } else if (reduce_mode == HX_REDUCE_SEQUENTIAL) {
         hipLaunchKernelGGL(k_sequential_max, dim3(1), dim3(64), 0, s, a,

@@ -54,6 +54,7 @@ struct SweepShape {
     static constexpr bool NEED_Z =
         MODE == SM_STORE || MODE == SM_MASK || MODE == SM_SPEC;
     static constexpr bool DO_MAX = MODE != SM_MASK;
+    static constexpr bool EAGER = MODE == SM_MAXONLY;  // see the steady state
     static_assert(TY % P == 0, "tile height must be a multiple of the ring period");
     static_assert(KS <= P, "the horizontal-blur ring must hold k rows");
 };
@@ -189,20 +190,25 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     float ew[P][C];   // B(x-1) + B(x+1)
     float dx[P][C];   // Sobel dx
     float sy[P][C];   // Sobel sy
-    float hmx[P][C];  // 3-wide max of L
-    float hmn[P][C];  // 3-wide min of L
+    uint32_t hz[P];   // per row: bit e = the 3-wide window at column e holds
+                      // an L > 0 (bits 0..C-1) / holds only L > 0 (bits 8..)
     float g2d[C];     // G^2 of the row waiting for its Z
     float gacc = 0.0f;
 
-    // One step; J = s mod P, DB/DC/DD: stages B, C, D are active.
-    auto step = [&](auto jt, auto dbt, auto dct, auto ddt, int s) {
+    // One step; J = s mod P, DB/DC/DD: stages B, C, D are active; LD: the
+    // step prefetches input row v + PF (every step but the last PF): 1
+    // always, 0 never, 2 decided at run time.
+    auto step = [&](auto jt, auto dbt, auto dct, auto ddt, auto ldt, int s) {
         constexpr int J = decltype(jt)::value;
         constexpr bool DB = decltype(dbt)::value != 0;
         constexpr bool DC = decltype(dct)::value != 0;
         constexpr bool DD = decltype(ddt)::value != 0;
+        constexpr int LD = decltype(ldt)::value;
         constexpr int J1 = (J + P - 1) % P, J2 = (J + P - 2) % P;
         const int v = y0 - HX + s;
-        if (s + PF < NS) load_row(v + PF, pf[(J + PF) % P]);
+        if constexpr (LD == 1) load_row(v + PF, pf[(J + PF) % P]);
+        if constexpr (LD == 2)
+            if (s + PF < NS) load_row(v + PF, pf[(J + PF) % P]);
 
         // ---- A: horizontal blur of input row v
         {
@@ -299,40 +305,37 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 }
                 if constexpr (S::NEED_Z) {
                     if constexpr (BX) fix_cols<C, HL, SW>(l, x0, xs, cbase, W);
-                    const float ll0 = lane_fetch<-1>(l[C - 1]);
-                    const float lr0 = lane_fetch<1>(l[0]);
+                    // Z needs only the sign of L: whether the 3x3 window
+                    // holds an L > 0 (its max is > 0) and whether it holds
+                    // only L > 0 (its min is > 0).  Kept as bits, C per row.
+                    uint32_t sg = 0;
 #pragma unroll
-                    for (int e = 0; e < C; ++e) {
-                        const float lf = e > 0 ? l[e - 1] : ll0;
-                        const float rt = e < C - 1 ? l[e + 1] : lr0;
-                        hmx[J][e] = max3f(lf, l[e], rt);
-                        hmn[J][e] = min3f(lf, l[e], rt);
-                    }
+                    for (int e = 0; e < C; ++e) sg |= (l[e] > 0.0f) ? (1u << e) : 0u;
+                    const uint32_t sl = (uint32_t)__builtin_amdgcn_mov_dpp(
+                        (int)sg, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+                    const uint32_t sr = (uint32_t)__builtin_amdgcn_mov_dpp(
+                        (int)sg, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+                    // Bit e + 1 of ext is column e; bits 0 and C + 1 the
+                    // neighbouring lanes' edge columns.
+                    const uint32_t ext =
+                        ((sl >> (C - 1)) & 1u) | (sg << 1) | ((sr & 1u) << (C + 1));
+                    constexpr uint32_t CM = (1u << C) - 1u;
+                    hz[J] = ((ext | (ext >> 1) | (ext >> 2)) & CM) |
+                            (((ext & (ext >> 1) & (ext >> 2)) & CM) << 8);
                     if constexpr (BY) {
-                        if (vl >= H) {
-#pragma unroll
-                            for (int e = 0; e < C; ++e) {
-                                hmx[J][e] = hmx[J1][e];
-                                hmn[J][e] = hmn[J1][e];
-                            }
-                        }
-                        if (vl == 0) {
-#pragma unroll
-                            for (int e = 0; e < C; ++e) {
-                                hmx[J1][e] = hmx[J][e];
-                                hmn[J1][e] = hmn[J][e];
-                            }
-                        }
+                        if (vl >= H) hz[J] = hz[J1];
+                        if (vl == 0) hz[J1] = hz[J];
                     }
                     // ---- D: Z of row vz = vl - 1, and the output
                     if constexpr (DD) {
                         const int vz = vl - 1;
                         if (!BY || ((vz >= y0) & (vz < ylim))) {
+                            const uint32_t any = hz[J2] | hz[J1] | hz[J];
+                            const uint32_t all = hz[J2] & hz[J1] & hz[J];
+                            const uint32_t zb = any & ~(all >> 8) & CM;
                             bool z[C];
 #pragma unroll
-                            for (int e = 0; e < C; ++e)
-                                z[e] = zero_cross(max3f(hmx[J2][e], hmx[J1][e], hmx[J][e]),
-                                                  min3f(hmn[J2][e], hmn[J1][e], hmn[J][e]));
+                            for (int e = 0; e < C; ++e) z[e] = (zb >> e) & 1u;
                             if constexpr (MODE == SM_STORE) {
                                 float code[C];
 #pragma unroll
@@ -358,24 +361,32 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                         if (ecol[e]) rp[e] = (uint8_t)m[e];
                                 }
                                 if constexpr (MODE == SM_SPEC) {
-                                    // List this lane's row if it set a bit:
-                                    // its C values of G^2, and the row with
-                                    // the set columns as low bits.
+                                    // List the lanes that set a bit in this
+                                    // row, packed in lane order after the
+                                    // tile's earlier entries: their C values
+                                    // of G^2, and row | lane | set columns.
                                     static_assert(C <= 4, "four set-bits per entry");
                                     uint32_t bits = 0;
 #pragma unroll
                                     for (int e = 0; e < C; ++e)
                                         bits |= ((m[e] != 0u) & (BX ? ecol[e] : lane_out))
                                                     ? (1u << e) : 0u;
-                                    if (bits) {
-                                        const int64_t idx = (int64_t)sp->n * 64 + lane;
-                                        const gptr<VecF<C>> q =
-                                            (gptr<VecF<C>>)(as_global(sp->code) + idx * C);
+                                    const uint64_t bal = __ballot(bits != 0u);
+                                    if (bal) {
+                                        if (bits) {
+                                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                                (uint32_t)(bal >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                                            const int64_t idx = (int64_t)(sp->n + below);
+                                            const gptr<VecF<C>> q =
+                                                (gptr<VecF<C>>)(as_global(sp->code) + idx * C);
 #pragma unroll
-                                        for (int e = 0; e < C; ++e) q->v[e] = g2d[e];
-                                        as_global(sp->row)[idx] =
-                                            (int32_t)(((uint32_t)(vz - y0) << 4) | bits);
-                                        sp->n += 1;
+                                            for (int e = 0; e < C; ++e) q->v[e] = g2d[e];
+                                            as_global(sp->row)[idx] =
+                                                (int32_t)(((uint32_t)(vz - y0) << 10) |
+                                                          ((uint32_t)lane << 4) | bits);
+                                        }
+                                        sp->n += (uint32_t)__builtin_popcountll(bal);
                                     }
                                 }
                             }
@@ -394,14 +405,33 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     static_for([&](auto st) {
         constexpr int s = decltype(st)::value;
         step(IC<s % P>{}, IC<(s >= 2 * R)>{}, IC<(s >= 2 * R + 2)>{},
-             IC<(s >= 2 * R + 4)>{}, s);
+             IC<(s >= 2 * R + 4)>{}, IC<(s + PF < NS)>{}, s);
     }, std::make_integer_sequence<int, NP>{});
-    // Steady state: every stage active, TY steps in groups of P.
-    for (int s0 = NP; s0 < NS; s0 += P) {
+    // Steady state: every stage active, TY steps in groups of P.  With
+    // S::EAGER every group but the last prefetches unconditionally, so no
+    // load is conditional at run time and the wait before each use allows
+    // the full prefetch depth in flight; the heavier modes keep the run-time
+    // check, which holds their registers within three waves per SIMD.
+    static_assert(PF <= P, "the last group holds every step without a prefetch");
+    if constexpr (S::EAGER) {
+        for (int s0 = NP; s0 < NS - P; s0 += P) {
+            static_for([&](auto jt) {
+                constexpr int jj = decltype(jt)::value;
+                step(IC<(NP + jj) % P>{}, IC<1>{}, IC<1>{}, IC<1>{}, IC<1>{}, s0 + jj);
+            }, std::make_integer_sequence<int, P>{});
+        }
         static_for([&](auto jt) {
             constexpr int jj = decltype(jt)::value;
-            step(IC<(NP + jj) % P>{}, IC<1>{}, IC<1>{}, IC<1>{}, s0 + jj);
+            step(IC<(NP + jj) % P>{}, IC<1>{}, IC<1>{}, IC<1>{}, IC<(jj + PF < P)>{},
+                 NS - P + jj);
         }, std::make_integer_sequence<int, P>{});
+    } else {
+        for (int s0 = NP; s0 < NS; s0 += P) {
+            static_for([&](auto jt) {
+                constexpr int jj = decltype(jt)::value;
+                step(IC<(NP + jj) % P>{}, IC<1>{}, IC<1>{}, IC<1>{}, IC<2>{}, s0 + jj);
+            }, std::make_integer_sequence<int, P>{});
+        }
     }
     if constexpr (!BX && !BY) gacc = gvalid ? gacc : 0.0f;
     gmax = __builtin_fmaxf(gmax, gacc);

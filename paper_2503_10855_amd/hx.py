@@ -293,7 +293,16 @@ class Server:
 
     def submit(self, img, arrival=None):
         """img: host float32 numpy array (H, W); a row-strided view (a crop)
-        is passed with its pitch, without a copy.  Returns a ticket."""
+        is passed with its pitch, without a copy.  Returns a ticket; raises
+        HxError (status HX_E_PENDING) if the pinned pool is full until
+        finished requests are polled."""
+        t = self.try_submit(img, arrival)
+        if t is None:
+            raise HxError(HX_E_PENDING, "hx_serve_submit")
+        return t
+
+    def try_submit(self, img, arrival=None):
+        """submit(), but None while the pinned pool is full."""
         import numpy as np
         a = img
         if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.ndim == 2
@@ -301,10 +310,13 @@ class Server:
                 and a.strides[0] >= 4 * a.shape[1]):
             a = np.ascontiguousarray(a, dtype=np.float32)
         t = _u64()
-        _check(_lib.hx_serve_submit(self._h, a.ctypes.data, a.shape[0], a.shape[1],
-                                    a.strides[0] // 4,
-                                    self.now() if arrival is None else arrival,
-                                    ctypes.byref(t)), "hx_serve_submit")
+        st = _lib.hx_serve_submit(self._h, a.ctypes.data, a.shape[0], a.shape[1],
+                                  a.strides[0] // 4,
+                                  self.now() if arrival is None else arrival,
+                                  ctypes.byref(t))
+        if st == HX_E_PENDING:
+            return None
+        _check(st, "hx_serve_submit")
         return t.value
 
     def poll(self, ticket, shape, out=None):

@@ -87,3 +87,36 @@ def test_serve_admission_respects_budget(hx):
     assert st["peak_bytes"] <= budget and st["completed"] == len(imgs)
     for (m, _), ref in zip(res, refs):
         assert np.array_equal(m, ref)
+
+
+def test_serve_submit_never_blocks(hx):
+    """A full pinned pool makes submit return at once (pending), not wait:
+    the pool is freed only by polling, which a single-threaded caller could
+    then never reach.  After the finished requests are collected the same
+    request goes in."""
+    side = 2048  # 16 MiB in + 4 MiB mask per request; the pool holds 64 MiB
+    imgs = [synth.image(side, side, 80, i) for i in range(5)]
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 23, max_images=4) as p:
+        with hx.Server(p, hbm_budget=48 << 20, streams=2, max_batch=2) as srv:
+            print("serve: filling the pinned pool", flush=True)
+            tickets = []
+            refused = None
+            for i, a in enumerate(imgs):
+                t = srv.try_submit(a)
+                if t is None:
+                    refused = i
+                    break
+                tickets.append(t)
+            assert refused is not None and refused >= 2, refused
+            with pytest.raises(hx.HxError) as ei:
+                srv.submit(imgs[refused])
+            assert ei.value.status == hx.HX_E_PENDING
+            shapes = [(side, side)] * len(tickets)
+            res = collect(srv, tickets, shapes)
+            t = srv.submit(imgs[refused])
+            last = collect(srv, [t], [(side, side)])[0]
+        ref = p.edge_detect(torch.from_numpy(imgs[refused]).cuda()).cpu().numpy()
+        refs = [p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs[:refused]]
+    assert np.array_equal(last[0], ref)
+    for (m, _), r in zip(res, refs):
+        assert np.array_equal(m, r)
