@@ -116,10 +116,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="batch", choices=("batch", "serve", "reduce"),
+    ap.add_argument("--mode", default="batch", choices=("batch", "serve", "reduce", "tune"),
                     help="batch: the batched step (default); serve: the continuous-"
                          "batching server under Poisson arrivals; reduce: the "
-                         "max-reduction ablation on the unfused per-image form")
+                         "max-reduction ablation on the unfused per-image form; tune: "
+                         "the autotuner's measurement of every schedule on the "
+                         "workload's first image shape")
     ap.add_argument("--workload", default="batch-64x1080p", choices=sorted(workloads()))
     ap.add_argument("--requests", type=int, default=20000, help="serve: requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -158,6 +160,8 @@ def main():
         return run_serve(args, hx)
     if args.mode == "reduce":
         return run_reduce(args, hx)
+    if args.mode == "tune":
+        return run_tune(args, hx)
 
     wl = workloads()[args.workload]()
     images = [wl.image(i) for i in range(len(wl.sizes))]
@@ -448,6 +452,40 @@ def run_reduce(args, hx):
             "config": {"workload": wl.name, "images": len(imgs), "pixels": wl.pixels,
                        "schedule": "64x16 tiles, fusion depth 1"},
             "variants": out}
+    print(json.dumps(line), flush=True)
+
+
+def run_tune(args, hx):
+    """Every candidate schedule (tile x fusion depth x pass structure) timed
+    by hx_autotune on one image of the workload's shape (per-image form)."""
+    import tempfile
+    from paper_2503_10855_amd import synth
+    wl = workloads()[args.workload]()
+    H, W = wl.sizes[0]
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.jsonl")
+        with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=wl.theta,
+                         max_pixels=H * W, max_images=1) as p:
+            print(f"tune: {H}x{W} k{wl.ksize}", file=sys.stderr, flush=True)
+            chosen = p.autotune(H, W, cache)
+        lines = [json.loads(x) for x in open(cache)]
+    rows = []
+    for x in lines:
+        if "trial" not in x:
+            continue
+        t = x["trial"]
+        ms = t["ms"]
+        rows.append({"schedule": t["schedule"], "ms": round(ms, 4),
+                     "mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1),
+                     "effective_gbs": round(PATH_BYTES_PER_PX * H * W / (ms * 1e-3) / 1e9, 1)})
+    rows.sort(key=lambda r: r["ms"])
+    line = {"metric": "autotuner sweep (per-image form)", "unit": "Mpixel/s",
+            "value": rows[0]["mpx_s"], "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "height": H, "width": W, "ksize": wl.ksize,
+                       "sigma": wl.sigma, "schedule_fields": "tile_w, tile_h, fusion_depth, "
+                       "pass_mode (1 store, 2 recompute, 3 speculate), reduce_mode"},
+            "chosen": list(chosen), "trials": rows}
     print(json.dumps(line), flush=True)
 
 

@@ -198,9 +198,11 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img,
 
 /* Time every candidate schedule on a synthetic H x W image on this
  * pipeline's device (blocking; allocates and frees its own test image),
- * keep the fastest for that shape class, and append it to the JSON cache
- * at cache_path (NULL = do not persist).  Later calls on images of the
- * same shape class use it unless a schedule is forced. */
+ * keep the fastest for that shape class, and append it to the JSON-lines
+ * cache at cache_path (NULL = do not persist), after one {"trial": ...}
+ * line per measured candidate (its schedule and best-of-three ms; the
+ * loader skips those).  Later calls on images of the same shape class use
+ * the chosen schedule unless a schedule is forced. */
 hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
                       const char* cache_path);
 

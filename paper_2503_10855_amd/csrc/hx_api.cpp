@@ -277,7 +277,13 @@ hx_status ctx_wait(BatchContext& c) {
 
 // Enqueue [reset, (pass 0,) pass 1, pass 2] for this context on stream s;
 // with `timed`, bracket each launch with the context's timing events
-// (ev_t: 0 reset 1 pass-0 4 pass-1 2 pass-2 3).
+// (ev_t: 0 reset 1 pass-0 4 pass-1 2 pass-2 3).  Each pass runs one wave
+// per item (workgroups of four waves): a grid sized to the batch measured
+// faster than persistent workgroups striding over the items.
+static int phase_grid(const BatchContext& c, int ph) {
+    return (int)std::max<int64_t>(1, (c.n_items[ph] + 3) / 4);
+}
+
 static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipStream_t s,
                                  bool timed = false) {
     const int ks = p->prm.ksize;
@@ -285,20 +291,23 @@ static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipS
     if (e == hipSuccess) e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[1], s);
     if (e == hipSuccess && pass == HX_PASS_SPECULATE)
-        e = launch_batch_phase(ks, pass, 0, c.table.ptr, p->taps, p->batch_grid[pass][0], s);
+        e = launch_batch_phase(ks, pass, 0, c.table.ptr, p->taps, phase_grid(c, 0), s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[4], s);
     if (e == hipSuccess)
-        e = launch_batch_phase(ks, pass, 1, c.table.ptr, p->taps, p->batch_grid[pass][1], s);
+        e = launch_batch_phase(ks, pass, 1, c.table.ptr, p->taps, phase_grid(c, 1), s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[2], s);
     if (e == hipSuccess)
-        e = launch_batch_phase(ks, pass, 2, c.table.ptr, p->taps, p->batch_grid[pass][2], s);
+        e = launch_batch_phase(ks, pass, 2, c.table.ptr, p->taps, phase_grid(c, 2), s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[3], s);
     return e;
 }
 
-// Capture the launches once per (context, pass mode, table address).
+// Capture the launches once per (context, pass mode, table address, item
+// counts).
 static hx_status ctx_graph(hx_pipeline* p, BatchContext& c, int pass) {
-    if (c.exec[pass] && c.graph_table[pass] == c.table.ptr) return HX_OK;
+    if (c.exec[pass] && c.graph_table[pass] == c.table.ptr &&
+        std::memcmp(c.graph_items[pass], c.n_items, sizeof c.n_items) == 0)
+        return HX_OK;
     if (c.exec[pass]) {
         (void)hipGraphExecDestroy(c.exec[pass]);
         (void)hipGraphDestroy(c.graph[pass]);
@@ -324,6 +333,7 @@ static hx_status ctx_graph(hx_pipeline* p, BatchContext& c, int pass) {
     c.graph[pass] = g;
     c.exec[pass] = ex;
     c.graph_table[pass] = c.table.ptr;
+    std::memcpy(c.graph_items[pass], c.n_items, sizeof c.n_items);
     return HX_OK;
 }
 
@@ -338,13 +348,6 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
     std::lock_guard<std::mutex> lk(p->batch_mu);
     if (pass < HX_PASS_STORE || pass > HX_PASS_SPECULATE)
         return fail(HX_E_INVALID, "pass_mode %d unknown", pass);
-    if (p->batch_grid[pass][1] <= 0) {
-        for (int ph = pass == HX_PASS_SPECULATE ? 0 : 1; ph < 3; ++ph) {
-            p->batch_grid[pass][ph] = batch_grid_size(p->device, ks, pass, ph);
-            if (p->batch_grid[pass][ph] <= 0)
-                return fail(HX_E_HIP, "cannot size the batched launch");
-        }
-    }
     BatchContext& c = p->ctx[p->next_ctx];
     p->next_ctx = (p->next_ctx + 1) % hx_pipeline::kContexts;
     hx_status st = ctx_init(p, c);
@@ -359,11 +362,14 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
         st = build_table(p, c, imgs, n, d_max, pass, geo, stream);
         if (st != HX_OK) return st;
     }
+    // A batch seen again on this context replays a captured graph; a new
+    // composition launches its kernels directly (capturing every new batch
+    // would cost more than it saves, e.g. when serving).
     static const bool no_graph = std::getenv("HX_NO_GRAPH") != nullptr;
     if (p->timing) {
         HX_TRY(enqueue_phases(p, c, pass, stream, true));
         p->last_timed_ctx = (int)(&c - p->ctx);
-    } else if (no_graph) {
+    } else if (no_graph || !same) {
         HX_TRY(enqueue_phases(p, c, pass, stream));
     } else {
         st = ctx_graph(p, c, pass);
@@ -445,6 +451,9 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
         for (int64_t t = 0; t < p0n[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
 
     HX_TRY(hipMemcpyAsync(c.table.ptr, h, bytes, hipMemcpyHostToDevice, stream));
+    c.n_items[0] = n0;
+    c.n_items[1] = n1;
+    c.n_items[2] = n2;
     c.last_imgs.assign(imgs, imgs + n);
     c.last_dmax = d_max;
     c.last_pass = pass;

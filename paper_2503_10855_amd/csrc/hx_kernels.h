@@ -148,11 +148,9 @@ int batch_p2_rows(int64_t W);
 hipError_t launch_batch_reset(const void* d_table, uint32_t* slots,
                               int max_images, hipStream_t s);
 // One pass (phase 0, 1 or 2) over the table's item list on `grid`
-// persistent workgroups.  Phase 0 exists for SPECULATE only.
+// workgroups of four waves.  Phase 0 exists for SPECULATE only.
 hipError_t launch_batch_phase(int ks, int pass_mode, int phase,
                               const void* d_table, const Taps& t, int grid,
                               hipStream_t s);
-// Workgroups of a phase kernel that fit on the device at once; 0 on error.
-int batch_grid_size(int device, int ks, int pass_mode, int phase);
 
 }  // namespace hx

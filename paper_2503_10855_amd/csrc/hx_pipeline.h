@@ -60,6 +60,8 @@ struct BatchContext {
     hipGraphExec_t exec[4] = {};
     hipGraph_t graph[4] = {};
     const void* graph_table[4] = {};
+    int64_t graph_items[4][3] = {};  // item counts baked into each graph
+    int64_t n_items[3] = {0, 0, 0};  // the table's items of pass 0, 1, 2
     // The call whose table the device copy holds: a repeat of the same
     // batch (same descriptors, outputs and pass mode) reuses it as is.
     std::vector<hx_image> last_imgs;
@@ -98,7 +100,6 @@ struct hx_pipeline {
     std::mutex batch_mu;  // guards context rotation (the server calls from
                           // its own thread)
     hipStream_t capture_stream = nullptr;
-    int batch_grid[4][3] = {};  // [pass mode][phase]
     bool timing = false;
     int last_timed_ctx = -1;
 };

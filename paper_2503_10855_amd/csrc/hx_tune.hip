@@ -53,6 +53,8 @@ std::vector<hx_schedule> candidates(int ks) {
                         c.push_back({tw, th, 4, HX_PASS_RECOMPUTE, HX_REDUCE_TREE});
                     }
                 }
+        // SPECULATE runs one tile shape (validate_schedule drops the others).
+        c.push_back({256, 64, 4, HX_PASS_SPECULATE, HX_REDUCE_TREE});
     }
     return c;
 }
@@ -108,6 +110,11 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char*
     hx_status st = HX_OK;
     const bool was_forced = p->forced;
     p->forced = false;
+    struct Trial {
+        hx_schedule s;
+        float ms;
+    };
+    std::vector<Trial> trials;
     for (const hx_schedule& c : candidates(p->prm.ksize)) {
         if (validate_schedule(p, c) != HX_OK) continue;
         // One warm-up call (allocates scratch), then the fastest of three.
@@ -129,6 +136,7 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char*
             std::fprintf(stderr, "tune %lldx%lld k%d: %dx%d depth %d pass %d: %.4f ms\n",
                          (long long)height, (long long)width, p->prm.ksize, c.tile_w, c.tile_h,
                          c.fusion_depth, c.pass_mode, ms_min);
+        trials.push_back({c, ms_min});
         if (ms_min < best_ms) {
             best_ms = ms_min;
             best = c;
@@ -145,6 +153,14 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char*
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(HX_E_INVALID, "cannot open autotune cache %s", cache_path);
+        // Every measured candidate first (lines the loader skips), then the
+        // chosen schedule.
+        for (const Trial& t : trials)
+            std::fprintf(f,
+                         "{\"trial\": {\"ksize\": %d, \"height\": %lld, \"width\": %lld, "
+                         "\"schedule\": [%d, %d, %d, %d, %d], \"ms\": %.5f}}\n",
+                         p->prm.ksize, (long long)height, (long long)width, t.s.tile_w,
+                         t.s.tile_h, t.s.fusion_depth, t.s.pass_mode, t.s.reduce_mode, t.ms);
         std::fprintf(f,
                      "{\"ksize\": %d, \"hb\": %d, \"wb\": %d, \"schedule\": [%d, %d, %d, %d, %d], "
                      "\"ms\": %.5f, \"height\": %lld, \"width\": %lld}\n",

@@ -14,9 +14,11 @@
 // re-decides only the listed pixels in pass 2 (one item = one pass-1 tile).
 // Pass 2 starts after pass 1 has finished (a kernel boundary), so every max
 // is final when it is read; no workgroup ever waits for another one.  Each
-// persistent wave strides over its pass's item list; the item lists live in
-// the descriptor table, so one captured graph serves every batch
-// composition.
+// wave takes the item of its index (the host sizes each grid to its pass's
+// item count; were a grid smaller, its waves would stride over the rest).
+// The item lists live in the descriptor table, so the kernels read every
+// size from it and a captured graph is replayed as long as the batch's
+// item counts are unchanged.
 #include <hip/hip_runtime.h>
 
 #include "../../include/hx.h"
@@ -250,16 +252,6 @@ static const void* batch_kernel_ptr(int ks, int pass, int phase) {
     return nullptr;
 }
 
-int batch_grid_size(int device, int ks, int pass_mode, int phase) {
-    const void* k = batch_kernel_ptr(ks, pass_mode, phase);
-    if (!k) return 0;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess)
-        return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        return 0;
-    return per_cu * cus;
-}
 
 hipError_t launch_batch_phase(int ks, int pass_mode, int phase, const void* d_table,
                               const Taps& t, int grid, hipStream_t s) {

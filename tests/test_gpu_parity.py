@@ -187,19 +187,41 @@ def test_single_kernel_wait_queue_batch(hx):
     raise AssertionError("switched off")
 
 
-def test_batched_graph_replay_with_changing_batches(hx):
-    """One captured graph serves batches of different compositions (the
-    kernel reads every size from the descriptor table)."""
-    with hx.Pipeline(theta=THETA) as p:
+@pytest.mark.parametrize("pass_mode", [2, 3])
+def test_batched_graph_replay_with_changing_batches(hx, pass_mode):
+    """Batches of different compositions on one pipeline: the first call of
+    a composition on a batch context launches directly, a repeat replays a
+    captured graph (re-captured when the item counts change).  Each
+    composition runs 8 times (more calls than contexts), with eager work
+    on the outputs between the calls; every result must be the first one,
+    which must match the oracle."""
+    with hx.Pipeline(theta=THETA, pass_mode=pass_mode) as p:
         for rep, sizes in enumerate([[(100, 200), (50, 50)],
                                      [(1, 1), (300, 301), (64, 64), (7, 900)],
-                                     [(100, 200)]]):
+                                     [(100, 200)],
+                                     [(100, 200), (50, 50)]]):
             imgs = [synth.image(h, w, 24 + rep, i) for i, (h, w) in enumerate(sizes)]
-            print(f"replay {rep}: launching", flush=True)
-            masks = p.edge_detect_batched([dev(a) for a in imgs])
-            p.sync()
-            for a, m in zip(imgs, masks):
-                assert_mask(m.cpu().numpy(), ora(a), f"replay {rep} {a.shape}")
+            srcs = [dev(a) for a in imgs]
+            masks = [torch.empty(a.shape, dtype=torch.uint8, device="cuda") for a in imgs]
+            dmax = torch.zeros(len(imgs), device="cuda")
+            batch = p.prepare_batch(srcs, masks, dmax)
+            first = None
+            for call in range(8):
+                print(f"replay {rep} call {call}: launching", flush=True)
+                for m in masks:
+                    m.fill_(7)
+                dmax.fill_(-1.0)
+                batch.run()
+                p.sync()
+                got = ([m.cpu().numpy() for m in masks], dmax.cpu().numpy())
+                if first is None:
+                    first = got
+                    for a, m in zip(imgs, got[0]):
+                        assert_mask(m, ora(a), f"replay {rep} {a.shape}")
+                else:
+                    for m0, m1 in zip(first[0], got[0]):
+                        assert np.array_equal(m0, m1), (rep, call)
+                    assert np.array_equal(first[1], got[1]), (rep, call)
 
 
 @pytest.mark.parametrize("sched", [(256, 64, 4, 1, 0), (64, 16, 1, 1, 0),

@@ -1,0 +1,53 @@
+"""The autotuner: every candidate schedule is measured, the fastest is kept
+for the shape class and persisted, and a pipeline that loads the cache uses
+it; results under the tuned schedule still match the oracle."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2503_10855_amd import synth
+
+pytestmark = pytest.mark.gpu
+THETA = 0.1
+
+
+@pytest.fixture(scope="module")
+def hx():
+    from paper_2503_10855_amd import hx as mod
+    return mod
+
+
+@pytest.mark.parametrize("ks,sigma", [(5, 1.0), (9, 2.0)])
+def test_autotune_choose_persist_reload(hx, tmp_path, ks, sigma):
+    H, W = 300, 700
+    cache = str(tmp_path / "tune.jsonl")
+    img = synth.image(H, W, 81, ks)
+    with hx.Pipeline(ksize=ks, sigma=sigma, theta=THETA, max_pixels=1 << 20) as p:
+        print(f"autotune {H}x{W} k{ks}", flush=True)
+        chosen = p.autotune(H, W, cache)
+        mask = p.edge_detect(torch.from_numpy(img).cuda()).cpu().numpy()
+    lines = [json.loads(x) for x in open(cache)]
+    trials = [x["trial"] for x in lines if "trial" in x]
+    entries = [x for x in lines if "trial" not in x]
+    assert len(entries) == 1 and tuple(entries[0]["schedule"]) == tuple(chosen)
+    # depth 1 always; the fused depths and pass structures for k in {3,5,7}
+    depths = {t["schedule"][2] for t in trials}
+    passes = {t["schedule"][3] for t in trials if t["schedule"][2] == 4}
+    if ks in (3, 5, 7):
+        assert depths == {1, 2, 3, 4} and passes == {1, 2, 3}
+    else:
+        assert depths == {1}
+    best = min(trials, key=lambda t: t["ms"])
+    assert tuple(best["schedule"]) == tuple(chosen)
+    assert all(t["ms"] > 0 for t in trials)
+    o = oracle.edge_detect(img, ks, sigma, THETA, stages=True)
+    r = parity.compare_mask(mask, o, THETA)
+    assert r["mismatch"] == 0, r
+    with hx.Pipeline(ksize=ks, sigma=sigma, theta=THETA, max_pixels=1 << 20) as q:
+        q.autotune_load(cache)
+        assert tuple(q.schedule(H + 50, W + 100)) == tuple(chosen)  # same shape class
+        assert np.array_equal(q.edge_detect(torch.from_numpy(img).cuda()).cpu().numpy(), mask)
