@@ -66,14 +66,15 @@ typedef struct hx_server hx_server;
  *              (G^2 where Z = 1, else -1) plus the max; pass 2 thresholds.
  *  RECOMPUTE:  pass 1 computes blur and Sobel only, for the max; pass 2
  *              recomputes every stage and writes the mask directly.
- *  SPECULATE:  pass 0 computes G^2 on sampled row bands (16 rows in every
- *              256) for a lower bound m <= max G^2 of each image; pass 1
- *              computes every stage once, writes the mask against the
- *              threshold of m (a pixel it leaves at 0 is 0 under the true
- *              max too) and lists the pixels it set, with their G^2;
- *              pass 2 re-decides only those against the true max.  Exact
- *              for every input; fast when the listed pixels are few.  Runs
- *              the 256 x 64 sweep tile only. */
+ *  SPECULATE:  pass 0 computes G^2 on sampled row bands (16 rows at the
+ *              top of every max(32, min(256, H/4)) rows) for a lower
+ *              bound m <= max G^2 of each image; pass 1 computes every
+ *              stage once, writes the mask against the threshold of m (a
+ *              pixel it leaves at 0 is 0 under the true max too) and lists
+ *              the pixels it set, with their G^2; pass 2 re-decides only
+ *              those against the true max.  Exact for every input; fast
+ *              when the listed pixels are few.  Runs the 256 x 64 sweep
+ *              tile only. */
 enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2,
        HX_PASS_SPECULATE = 3 };
 

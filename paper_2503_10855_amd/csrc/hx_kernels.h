@@ -133,10 +133,15 @@ struct BatchHeader {
 
 size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2,
                          int64_t n_items0);
-// SPECULATE: pass-0 band geometry (16 sampled rows at the top of every 256)
-// and the listed-pixel capacity of one pass-1 item, in entries.
+// SPECULATE: pass-0 band geometry (16 sampled rows at the top of every
+// sample_stride(H) rows: every 256 rows of a tall image, at least four
+// bands in a shorter one) and the listed-pixel capacity of one pass-1 item,
+// in entries.
 constexpr int kSampleRows = 16;
-constexpr int kSampleStride = 256;
+__host__ __device__ inline int sample_stride(int64_t H) {
+    const int64_t s = H / 4;
+    return s < 32 ? 32 : (s > 256 ? 256 : (int)s);
+}
 int64_t batch_sample_items(int ks, int64_t H, int64_t W);
 int64_t batch_spec_entries();  // 64 * TY
 int batch_sweep_c();   // columns per lane of the batch sweep

@@ -55,7 +55,8 @@ size_t batch_table_bytes(int n, int64_t n1, int64_t n2, int64_t n0) {
 
 int64_t batch_sample_items(int ks, int64_t H, int64_t W) {
     const SweepGeom g{ks, kBC, kSampleRows};
-    return g.strips(W) * ((H + kSampleStride - 1) / kSampleStride);
+    const int st = sample_stride(H);
+    return g.strips(W) * ((H + st - 1) / st);
 }
 
 int64_t batch_spec_entries() { return 64 * kBTY; }
@@ -114,7 +115,7 @@ void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
         const int nstrips = (a.W + S::OW - 1) / S::OW;
         float gmax = 0.0f;
         sweep_tile<KS, kBC, kSampleRows, SM_MAXONLY>(
-            a, tp, (it.local % nstrips) * S::OW, (it.local / nstrips) * kSampleStride, 0.0f,
+            a, tp, (it.local % nstrips) * S::OW, (it.local / nstrips) * sample_stride(a.H), 0.0f,
             gmax);
         gmax = wave_max(gmax);
         if (lane_id() == 0) atomic_max_g2(tv.hdr.bound + it.image, gmax);
@@ -201,6 +202,8 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
             const int x0 = (it.local % nstrips) * S::OW;
             const int y0 = (it.local / nstrips) * kBTY;
             const int n = (int)as_global(tv.hdr.cand_n)[k];
+            const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &
+                              ((a.mp % 4) == 0);
             const int64_t base = (int64_t)k * (64 * kBTY);
             for (int t = lane; t < n; t += 64) {
                 const int64_t idx = base + t;
@@ -210,9 +213,20 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
                 const int y = y0 + (int)(rw >> 10);
                 const int cbase = x0 - S::HL + kBC * (int)((rw >> 4) & 63u);
                 const gptr<uint8_t> rp = as_global(a.mask) + (int64_t)y * a.mp + cbase;
+                // A column whose bit is clear holds 0 already (pass 1 left it
+                // there), so the lane-row is rewritten whole when it is one
+                // aligned word inside the image: one store, not one per byte.
+                uint32_t w = 0;
 #pragma unroll
                 for (int e = 0; e < kBC; ++e)
-                    if ((rw >> e) & 1u) rp[e] = q->v[e] > thr2 ? 1 : 0;
+                    w |= (((rw >> e) & 1u) && q->v[e] > thr2) ? (1u << (8 * e)) : 0u;
+                if (kBC == 4 && mvec && cbase + 4 <= a.W) {
+                    *(gptr<uint32_t>)rp = w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kBC; ++e)
+                        if ((rw >> e) & 1u) rp[e] = (uint8_t)(w >> (8 * e));
+                }
             }
         } else {
             const int nstrips = (a.W + S::OW - 1) / S::OW;

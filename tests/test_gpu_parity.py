@@ -135,16 +135,17 @@ def test_batched_equals_per_image(hx, ks, sigma, pass_mode):
 
 
 def weak_bound_images():
-    """Images on which the sampled bands of SPECULATE (16 rows in every 256)
-    see a poor lower bound of the max, or none at all, so pass 1 lists many
-    or most pixels: the strongest edge sits between the bands, or the bands
-    are flat (bound 0: every pixel with Z = 1 and G > 0 is listed)."""
+    """Images on which the sampled bands of SPECULATE (16 rows at the top of
+    every max(32, min(256, H // 4)) rows) see a poor lower bound of the max,
+    or none at all, so pass 1 lists many or most pixels: the strongest edge
+    sits between the bands, or the bands are flat (bound 0: every pixel
+    with Z = 1 and G > 0 is listed)."""
     out = []
-    a = synth.image(300, 700, 26, 0) * 0.2
-    a[60:90, 200:260] += 5.0            # the strongest edge, rows 16..255
+    a = synth.image(300, 700, 26, 0) * 0.2  # bands at rows 0, 75, 150, 225
+    a[30:60, 200:260] += 5.0            # the strongest edge, between bands
     out.append(a.astype(np.float32))
     b = synth.image(290, 513, 26, 1)
-    for y0 in range(0, 290, 256):       # flat over each band and its halo
+    for y0 in range(0, 290, 72):        # flat over each band and its halo
         b[max(0, y0 - 4):y0 + 20] = 0.3
     out.append(b.astype(np.float32))
     rng = np.random.default_rng(np.random.SeedSequence([26, 2]))
