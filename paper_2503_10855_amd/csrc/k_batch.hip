@@ -183,9 +183,12 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
     for (int k = global_wave(); k < tv.hdr.n_items2; k += nw) {
         const BatchItem it = tv.items2[k];
         const ImgArgs a = tv.imgs[it.image];
-        const uint32_t m2 = *a.slot;
+        // SPECULATE: the tile's entry count, loaded beside the max.
+        int n_listed = 0;
+        if constexpr (PASS == HX_PASS_SPECULATE) n_listed = (int)as_global(tv.hdr.cand_n)[k];
+        const uint32_t m2 = *as_global(a.slot);
         const float thr2 = thr2_from(m2, tv.hdr.theta);
-        if (it.local == 0 && lane == 0 && a.dmax) *a.dmax = max_from(m2);
+        if (it.local == 0 && lane == 0 && a.dmax) *as_global(a.dmax) = max_from(m2);
         if constexpr (PASS == HX_PASS_STORE) {
             const int rb = p2_rows(a.W);
             const int r0 = it.local * rb;
@@ -201,7 +204,7 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             const int x0 = (it.local % nstrips) * S::OW;
             const int y0 = (it.local / nstrips) * kBTY;
-            const int n = (int)as_global(tv.hdr.cand_n)[k];
+            const int n = n_listed;
             const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &
                               ((a.mp % 4) == 0);
             const int64_t base = (int64_t)k * (64 * kBTY);
@@ -213,19 +216,34 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
                 const int y = y0 + (int)(rw >> 10);
                 const int cbase = x0 - S::HL + kBC * (int)((rw >> 4) & 63u);
                 const gptr<uint8_t> rp = as_global(a.mask) + (int64_t)y * a.mp + cbase;
-                // A column whose bit is clear holds 0 already (pass 1 left it
-                // there), so the lane-row is rewritten whole when it is one
-                // aligned word inside the image: one store, not one per byte.
-                uint32_t w = 0;
+                // Pass 1 set every listed pixel to 1 and left the others of
+                // the lane-row at 0.  Only a listed pixel at or below the
+                // true threshold changes (to 0): the lane-row is rewritten,
+                // as one aligned word when it lies inside the image, only
+                // if one did.  Those are few when the bound is close to the
+                // max, and scattered partial writes are what this pass
+                // spends its time on.
+                // Both loads are unconditional, so they are in flight
+                // together (a short-circuit test would load each value
+                // behind its own wait).
+                float g2v[kBC];
 #pragma unroll
-                for (int e = 0; e < kBC; ++e)
-                    w |= (((rw >> e) & 1u) && q->v[e] > thr2) ? (1u << (8 * e)) : 0u;
-                if (kBC == 4 && mvec && cbase + 4 <= a.W) {
-                    *(gptr<uint32_t>)rp = w;
-                } else {
+                for (int e = 0; e < kBC; ++e) g2v[e] = q->v[e];
+                uint32_t w = 0, was = 0;
 #pragma unroll
-                    for (int e = 0; e < kBC; ++e)
-                        if ((rw >> e) & 1u) rp[e] = (uint8_t)(w >> (8 * e));
+                for (int e = 0; e < kBC; ++e) {
+                    const uint32_t listed = (rw >> e) & 1u;
+                    was |= listed << (8 * e);
+                    w |= (listed & (uint32_t)(g2v[e] > thr2)) << (8 * e);
+                }
+                if (w != was) {
+                    if (kBC == 4 && mvec && cbase + 4 <= a.W) {
+                        *(gptr<uint32_t>)rp = w;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < kBC; ++e)
+                            if (((was ^ w) >> (8 * e)) & 1u) rp[e] = 0;
+                    }
                 }
             }
         } else {
