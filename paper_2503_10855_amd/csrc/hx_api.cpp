@@ -242,8 +242,7 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
 // ------------------------------------------------------------- batched --
 static hx_status ctx_init(hx_pipeline* p, BatchContext& c) {
     if (c.ready) return HX_OK;
-    // Max slots, then (SPECULATE) as many bound slots.
-    HX_TRY(hipMalloc(&c.slots, 2 * sizeof(uint32_t) * p->prm.max_images));
+    HX_TRY(hipMalloc(&c.slots, sizeof(uint32_t) * p->prm.max_images));
     HX_TRY(hipEventCreateWithFlags(&c.ev_done, hipEventDisableTiming));
     for (auto& e : c.ev_t) HX_TRY(hipEventCreate(&e));
     c.ready = true;
@@ -262,6 +261,7 @@ static void ctx_release(BatchContext& c) {
     c.cand_n.release();
     if (c.h_table) (void)hipHostFree(c.h_table);
     if (c.slots) (void)hipFree(c.slots);
+    if (c.spec_state) (void)hipFree(c.spec_state);
     if (c.ev_done) (void)hipEventDestroy(c.ev_done);
     for (auto& e : c.ev_t)
         if (e) (void)hipEventDestroy(e);
@@ -275,7 +275,8 @@ hx_status ctx_wait(BatchContext& c) {
     return HX_OK;
 }
 
-// Enqueue [reset, (pass 0,) pass 1, pass 2] for this context on stream s;
+// Enqueue [reset, pass 1, pass 2] (SPECULATE: [pass 0, pass 1, pass 2])
+// for this context on stream s;
 // with `timed`, bracket each launch with the context's timing events
 // (ev_t: 0 reset 1 pass-0 4 pass-1 2 pass-2 3).  Each pass runs one wave
 // per item (workgroups of four waves): a grid sized to the batch measured
@@ -288,7 +289,8 @@ static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipS
                                  bool timed = false) {
     const int ks = p->prm.ksize;
     hipError_t e = timed ? hipEventRecord(c.ev_t[0], s) : hipSuccess;
-    if (e == hipSuccess) e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
+    if (e == hipSuccess && pass != HX_PASS_SPECULATE)
+        e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[1], s);
     if (e == hipSuccess && pass == HX_PASS_SPECULATE)
         e = launch_batch_phase(ks, pass, 0, c.table.ptr, p->taps, phase_grid(c, 0), s);
@@ -405,6 +407,12 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
     if (n1 >= (int64_t(1) << 31) || n2 >= (int64_t(1) << 31) || n0 >= (int64_t(1) << 31))
         return fail(HX_E_INVALID, "batch has too many work items");
     if (pass == HX_PASS_STORE) HX_TRY(c.code.ensure((size_t)code_elems * sizeof(float)));
+    if (spec && !c.spec_state) {
+        // Bounds (8 B each) and the epoch, cleared once by a fill kernel.
+        const int64_t words = 2 * p->prm.max_images + 2;
+        HX_TRY(hipMalloc(&c.spec_state, sizeof(uint32_t) * words));
+        HX_TRY(launch_fill_u32((uint32_t*)c.spec_state, 0u, words, stream));
+    }
     if (spec) {
         const size_t entries = (size_t)n1 * batch_spec_entries();
         HX_TRY(c.cand_code.ensure(entries * geo.c * sizeof(float)));
@@ -434,7 +442,8 @@ static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* im
         hdr.cand_code = (float*)c.cand_code.ptr;
         hdr.cand_row = (int32_t*)c.cand_row.ptr;
         hdr.cand_n = (uint32_t*)c.cand_n.ptr;
-        hdr.bound = c.slots + p->prm.max_images;
+        hdr.bound = (unsigned long long*)c.spec_state;
+        hdr.epoch = (uint32_t*)(hdr.bound + p->prm.max_images);
     }
     std::memcpy(h, &hdr, sizeof hdr);
     ImgArgs* ia = (ImgArgs*)(h + sizeof(BatchHeader));

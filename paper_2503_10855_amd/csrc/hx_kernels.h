@@ -126,9 +126,13 @@ struct BatchHeader {
     float* cand_code;
     int32_t* cand_row;
     uint32_t* cand_n;
-    // SPECULATE: per-image lower bounds of max G^2 (bits), written by pass
-    // 0 and only read by pass 1, whose own maxima go to the images' slots.
-    uint32_t* bound;
+    // SPECULATE: per-image lower bounds of max G^2, written by pass 0 and
+    // only read by pass 1 (whose own maxima go to the images' slots).  A
+    // bound is (epoch << 32) | bits of G^2: pass 0 folds values of the
+    // current epoch with a 64-bit max, so a bound left by an earlier batch
+    // needs no clearing (its epoch is lower); pass 2 advances the epoch.
+    unsigned long long* bound;
+    uint32_t* epoch;
 };
 
 size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2,
@@ -148,8 +152,8 @@ int batch_sweep_c();   // columns per lane of the batch sweep
 int batch_sweep_ty();  // rows per batch sweep tile
 // Rows per pass-2 item of the STORE threshold for width W.
 int batch_p2_rows(int64_t W);
-// Zero the first n (read from the table) max slots, and as many bound
-// slots when the table has them; grid sized for max_images.
+// Zero the first n (read from the table) max slots; grid sized for
+// max_images.  SPECULATE batches do not need it (pass 0 clears them).
 hipError_t launch_batch_reset(const void* d_table, uint32_t* slots,
                               int max_images, hipStream_t s);
 // One pass (phase 0, 1 or 2) over the table's item list on `grid`

@@ -50,6 +50,7 @@ struct BatchContext {
     void* h_table = nullptr;    // pinned staging copy of the table
     size_t h_table_bytes = 0;
     uint32_t* slots = nullptr;  // max_images max slots
+    void* spec_state = nullptr; // SPECULATE: max_images bounds, the epoch
     DevBuf code;                // pass-1 store buffer
     DevBuf cand_code, cand_row, cand_n;  // SPECULATE: listed pixels
     hipEvent_t ev_done = nullptr;

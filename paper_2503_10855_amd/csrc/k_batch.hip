@@ -85,13 +85,9 @@ __device__ __forceinline__ TableView view(const uint8_t* __restrict__ table) {
 }
 
 __global__ void k_batch_reset(const uint8_t* __restrict__ table, uint32_t* slots) {
-    const BatchHeader* h = reinterpret_cast<const BatchHeader*>(table);
-    const int n = h->n_images;
-    uint32_t* bound = h->bound;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int n = reinterpret_cast<const BatchHeader*>(table)->n_images;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         slots[i] = 0;
-        if (bound) bound[i] = 0;
-    }
 }
 
 // Index of this wave among all waves of the grid (XCD-contiguous).
@@ -101,24 +97,30 @@ __device__ __forceinline__ int global_wave() {
 }
 
 // SPECULATE pass 0: G^2 on the sampled bands, folded into the images'
-// bound slots.  Any pixel's G^2 is at most the image's max, so each then
-// holds a lower bound of it.
+// bounds under the current epoch.  Any pixel's G^2 is at most the image's
+// max, so each then holds a lower bound of it.  The first item of each
+// image also clears the image's max slot (pass 1 folds into it after this
+// kernel), so SPECULATE needs no reset kernel.
 template <int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
     using S = SweepShape<KS, kBC, kSampleRows, SM_MAXONLY>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
+    const uint64_t ep = (uint64_t)*as_global(tv.hdr.epoch) << 32;
     for (int k = global_wave(); k < tv.hdr.n_items0; k += nw) {
         const BatchItem it = tv.items0[k];
         const ImgArgs a = tv.imgs[it.image];
+        if (it.local == 0 && lane_id() == 0) *as_global(a.slot) = 0u;
         const int nstrips = (a.W + S::OW - 1) / S::OW;
         float gmax = 0.0f;
         sweep_tile<KS, kBC, kSampleRows, SM_MAXONLY>(
             a, tp, (it.local % nstrips) * S::OW, (it.local / nstrips) * sample_stride(a.H), 0.0f,
             gmax);
         gmax = wave_max(gmax);
-        if (lane_id() == 0) atomic_max_g2(tv.hdr.bound + it.image, gmax);
+        if (lane_id() == 0)
+            atomicMax(tv.hdr.bound + it.image,
+                      (unsigned long long)(ep | __float_as_uint(gmax)));
     }
 }
 
@@ -143,7 +145,9 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
             // the bounds meanwhile.  (Reading the image's slot, which the
             // other tiles keep raising, measured much slower: each read
             // waits behind this wave's own atomic on the same address.)
-            const uint32_t lb2 = as_global(tv.hdr.bound)[it.image];
+            const uint64_t bv = as_global(tv.hdr.bound)[it.image];
+            const uint32_t lb2 = (uint32_t)(bv >> 32) == *as_global(tv.hdr.epoch)
+                                     ? (uint32_t)bv : 0u;
             thr2 = thr2_from(lb2, tv.hdr.theta) * kSpecSafety;
             const int64_t base = (int64_t)k * (64 * kBTY);
             sp.code = tv.hdr.cand_code + base * kBC;
@@ -205,6 +209,9 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
             const int x0 = (it.local % nstrips) * S::OW;
             const int y0 = (it.local / nstrips) * kBTY;
             const int n = n_listed;
+            // The last reader of this batch's bounds has finished: advance
+            // the epoch for the next batch on this context.
+            if (k == 0 && lane == 0) *as_global(tv.hdr.epoch) += 1u;
             const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &
                               ((a.mp % 4) == 0);
             const int64_t base = (int64_t)k * (64 * kBTY);

@@ -179,6 +179,31 @@ def test_speculate_with_weak_bound(hx, ks, sigma):
         assert_mask(res[3][0][i], ora(a, ks, sigma), f"weak bound {i} {a.shape}")
 
 
+def test_speculate_bounds_never_leak_between_batches(hx):
+    """SPECULATE's bounds persist in each batch context and are told apart
+    by an epoch; a bound left by an earlier batch with a brighter image in
+    the same slot must never be used (it would exceed the dim image's max
+    and clear its edges).  Alternate bright and dim batches over every
+    context, twice, and compare with the per-image result each time."""
+    bright = synth.image(200, 300, 27, 0) * 8.0
+    dim = synth.image(200, 300, 27, 1) * 0.5
+    refs = {}
+    with hx.Pipeline(theta=THETA, pass_mode=3) as p:
+        for name, a in (("bright", bright), ("dim", dim)):
+            p.set_schedule(64, 16, 1)  # depth 1: no bound involved
+            refs[name] = p.edge_detect(dev(a)).cpu().numpy()
+            p.set_schedule()
+        for call in range(14):
+            name, a = (("bright", bright), ("dim", dim))[call % 2]
+            print(f"epoch test call {call}: {name}", flush=True)
+            m = p.edge_detect_batched([dev(a), dev(dim)])
+            p.sync()
+            assert np.array_equal(m[0].cpu().numpy(), refs[name]), (call, name)
+            assert np.array_equal(m[1].cpu().numpy(), refs["dim"]), call
+    assert refs["dim"].sum() > 0
+    assert_mask(refs["dim"], ora(dim), "dim")
+
+
 @pytest.mark.skip(reason="the single-kernel batched variant, in which pass-2 "
                   "workgroups spin until their image's pass-1 items are done, "
                   "went silent on the GPU twice (the second time after its "
