@@ -1,6 +1,6 @@
 """Parity at the full benchmark workload sizes, in the launch configuration
-the benchmark times (the batched persistent launch with the default
-schedule), against the oracle on every image."""
+the benchmark times (the batched call with its default pass structure),
+against the oracle on every image."""
 import concurrent.futures as cf
 import os
 

@@ -274,6 +274,28 @@ def test_pitch_and_misalignment(hx, sched):
     assert_mask(ref.cpu().numpy(), ora(img), "pitch")
 
 
+@pytest.mark.parametrize("ks,sigma", [(5, 1.0), (7, 1.5)])
+def test_extreme_aspect_ratios(hx, ks, sigma):
+    """One-row, one-column and very thin images, far longer than a sweep
+    strip or band in one direction: per image, and batched under every pass
+    structure, against the oracle."""
+    shapes = [(1, 70001), (70001, 1), (2, 40000), (40000, 3), (5, 4099), (4099, 6)]
+    imgs = [synth.image(h, w, 28, i) for i, (h, w) in enumerate(shapes)]
+    os_ = ora_many(imgs, ks, sigma)
+    srcs = [dev(a) for a in imgs]
+    for pm in (1, 2, 3):
+        with hx.Pipeline(ksize=ks, sigma=sigma, theta=THETA, pass_mode=pm) as p:
+            print(f"extreme shapes ks={ks} pass={pm}", flush=True)
+            masks = p.edge_detect_batched(srcs)
+            one = [p.edge_detect(s) for s in srcs]
+            p.sync()
+            torch.cuda.synchronize()
+            for i, (m, m1, o) in enumerate(zip(masks, one, os_)):
+                m = m.cpu().numpy()
+                assert np.array_equal(m, m1.cpu().numpy()), (pm, shapes[i])
+                assert_mask(m, o, f"pass {pm} {shapes[i]}")
+
+
 def test_degenerate_images(hx):
     with hx.Pipeline(theta=THETA) as p:
         for val in (0.0, 0.37):
