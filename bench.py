@@ -475,7 +475,7 @@ def run_tune(args, hx):
             continue
         t = x["trial"]
         ms = t["ms"]
-        rows.append({"schedule": t["schedule"], "ms": round(ms, 4),
+        rows.append({"schedule": t["schedule"], "text": t.get("text"), "ms": round(ms, 4),
                      "mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1),
                      "effective_gbs": round(PATH_BYTES_PER_PX * H * W / (ms * 1e-3) / 1e9, 1)})
     rows.sort(key=lambda r: r["ms"])

@@ -161,6 +161,31 @@ hx_status hx_pipeline_sync(hx_pipeline* p);
 hx_status hx_pipeline_set_timing(hx_pipeline* p, int enable);
 hx_status hx_pipeline_last_timing(hx_pipeline* p, float* ms);
 
+/* The scheduling language.  A schedule is a list of transformations of the
+ * EDGE fork-joins (labels blur, laplacian, zero_cross, sobel, max_gradient,
+ * threshold; each initially its own kernel, max_gradient a sequential
+ * reduction), in the manner of the Juno scheduling language (The Juno
+ * Scheduling Language; the reduction_tree macro of Use and Impact of
+ * Schedules), each statement ending with ';':
+ *   fork-tile[rows, cols](labels);      fork-fuse(labels);
+ *   fork-chunk[N](max_gradient);        fork-reshape(max_gradient);
+ *   monoid-reassociate(max_gradient);   fork-fission(max_gradient);
+ *   reduction_tree![N](max_gradient);   (the four steps above)
+ *   warp-reduce(max_gradient);          (wave64 primitives + one atomic
+ *                                        per wave)
+ *   pass[store|recompute|speculate](threshold);
+ * hx_schedule_compile applies them and lowers the result onto the kernels
+ * that exist: HX_OK and *out set, HX_E_INVALID for text that does not
+ * parse or a transformation that does not apply (e.g. fission of an
+ * unchunked reduction), HX_E_UNSUPPORTED for a program no kernel
+ * implements (e.g. fusing blur with laplacian only); hx_last_error says
+ * which statement and why.  Tile values are checked later, by
+ * hx_pipeline_set_schedule.  Needs no device.
+ * hx_schedule_to_text writes the canonical text of a schedule (NUL-
+ * terminated, at most len bytes; HX_E_INVALID if it does not fit). */
+hx_status hx_schedule_compile(const char* text, hx_schedule* out);
+hx_status hx_schedule_to_text(const hx_schedule* s, char* buf, size_t len);
+
 /* Force a schedule for every later call (NULL restores automatic choice).
  * HX_E_INVALID for knob values outside the sets documented above,
  * HX_E_UNSUPPORTED for a fused depth with ksize not in {3,5,7}. */

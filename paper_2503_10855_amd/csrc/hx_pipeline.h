@@ -18,6 +18,9 @@ namespace hx {
 // Thread-local error text behind hx_last_error().
 void set_error(const char* fmt, ...);
 hx_status fail(hx_status st, const char* fmt, ...);
+// The scheduling language (hx_sched.cpp): text -> schedule, and back.
+hx_status compile_schedule(const char* text, hx_schedule* out);
+std::string schedule_text(const hx_schedule& s);
 hx_status hip_fail(hipError_t e, const char* what);
 
 // Make `dev` current for the lifetime of the guard.

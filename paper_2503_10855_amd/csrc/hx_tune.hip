@@ -38,23 +38,44 @@ __global__ void k_tune_image(float* img, int64_t pitch, int H, int W) {
     }
 }
 
+// The candidates are schedule programs (see hx_schedule_compile): every
+// tile of the unfused stages, and every fusion grouping x sweep tile x
+// pass structure, each reducing the max with wave primitives.
 std::vector<hx_schedule> candidates(int ks) {
-    std::vector<hx_schedule> c;
+    std::vector<std::string> texts;
+    char b[160];
     for (int tw : {16, 32, 64})
-        for (int th : {16, 32}) c.push_back({tw, th, 1, HX_PASS_STORE, HX_REDUCE_TREE});
+        for (int th : {16, 32}) {
+            std::snprintf(b, sizeof b,
+                          "fork-tile[%d, %d](blur, laplacian, zero_cross, sobel); ", th, tw);
+            texts.push_back(std::string(b) + "warp-reduce(max_gradient);");
+        }
     if (ks == 3 || ks == 5 || ks == 7) {
-        for (int depth : {2, 3, 4})
+        const char* fuse[3] = {"fork-fuse(blur, sobel); fork-fuse(laplacian, zero_cross); ",
+                               "fork-fuse(blur, sobel, laplacian); ",
+                               "fork-fuse(blur, sobel, laplacian, zero_cross); "};
+        for (int depth = 2; depth <= 4; ++depth)
             for (int tw : {64, 128, 256})
                 for (int th : {16, 32, 64, 128}) {
+                    std::snprintf(b, sizeof b, "fork-tile[%d, %d](blur); ", th, tw);
+                    const std::string t =
+                        std::string(fuse[depth - 2]) + b + "warp-reduce(max_gradient);";
                     if (depth < 4) {
-                        c.push_back({tw, th, depth, HX_PASS_STORE, HX_REDUCE_TREE});
+                        texts.push_back(t);
                     } else {
-                        c.push_back({tw, th, 4, HX_PASS_STORE, HX_REDUCE_TREE});
-                        c.push_back({tw, th, 4, HX_PASS_RECOMPUTE, HX_REDUCE_TREE});
+                        texts.push_back(t + " pass[store](threshold);");
+                        texts.push_back(t + " pass[recompute](threshold);");
                     }
                 }
-        // SPECULATE runs one tile shape (validate_schedule drops the others).
-        c.push_back({256, 64, 4, HX_PASS_SPECULATE, HX_REDUCE_TREE});
+        // SPECULATE runs one tile shape.
+        texts.push_back(std::string(fuse[2]) +
+                        "fork-tile[64, 256](blur); warp-reduce(max_gradient); "
+                        "pass[speculate](threshold);");
+    }
+    std::vector<hx_schedule> c;
+    for (const std::string& t : texts) {
+        hx_schedule s{};
+        if (compile_schedule(t.c_str(), &s) == HX_OK) c.push_back(s);
     }
     return c;
 }
@@ -158,9 +179,11 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char*
         for (const Trial& t : trials)
             std::fprintf(f,
                          "{\"trial\": {\"ksize\": %d, \"height\": %lld, \"width\": %lld, "
-                         "\"schedule\": [%d, %d, %d, %d, %d], \"ms\": %.5f}}\n",
+                         "\"schedule\": [%d, %d, %d, %d, %d], \"ms\": %.5f, "
+                         "\"text\": \"%s\"}}\n",
                          p->prm.ksize, (long long)height, (long long)width, t.s.tile_w,
-                         t.s.tile_h, t.s.fusion_depth, t.s.pass_mode, t.s.reduce_mode, t.ms);
+                         t.s.tile_h, t.s.fusion_depth, t.s.pass_mode, t.s.reduce_mode, t.ms,
+                         schedule_text(t.s).c_str());
         std::fprintf(f,
                      "{\"ksize\": %d, \"hb\": %d, \"wb\": %d, \"schedule\": [%d, %d, %d, %d, %d], "
                      "\"ms\": %.5f, \"height\": %lld, \"width\": %lld}\n",

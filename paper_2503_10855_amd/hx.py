@@ -81,6 +81,9 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
     "hx_serve_now": (ctypes.c_double, [_P]),
+    "hx_schedule_compile": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Schedule)]),
+    "hx_schedule_to_text": (ctypes.c_int, [ctypes.POINTER(Schedule), ctypes.c_char_p,
+                                           ctypes.c_size_t]),
     "hx_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                       ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "hx_serve_destroy": (ctypes.c_int, [_P]),
@@ -134,6 +137,22 @@ def image_desc(src: torch.Tensor, mask: torch.Tensor) -> Image:
     return Image(src.data_ptr(), H, W, src.stride(0), mask.data_ptr(), mask.stride(0))
 
 
+def compile_schedule(text):
+    """Schedule text -> (tile_w, tile_h, fusion_depth, pass_mode,
+    reduce_mode); HxError if it does not parse, apply or lower."""
+    s = Schedule()
+    _check(_lib.hx_schedule_compile(text.encode(), ctypes.byref(s)), "hx_schedule_compile")
+    return s.astuple()
+
+
+def schedule_text(sched):
+    """The canonical schedule text of a (tile_w, tile_h, depth, pass, reduce)."""
+    s = Schedule(*sched)
+    buf = ctypes.create_string_buffer(1024)
+    _check(_lib.hx_schedule_to_text(ctypes.byref(s), buf, len(buf)), "hx_schedule_to_text")
+    return buf.value.decode()
+
+
 class Pipeline:
     """An hx_pipeline: constants, dynamic-constant sizes and scratch."""
 
@@ -178,6 +197,10 @@ class Pipeline:
         s = Schedule(tile_w, tile_h, fusion_depth, pass_mode, reduce_mode)
         _check(_lib.hx_pipeline_set_schedule(self._h, ctypes.byref(s)),
                "set_schedule")
+
+    def set_schedule_text(self, text):
+        """Force the schedule a schedule program compiles to."""
+        self.set_schedule(*compile_schedule(text))
 
     def schedule(self, H, W):
         s = Schedule()

@@ -43,6 +43,9 @@ def test_autotune_choose_persist_reload(hx, tmp_path, ks, sigma):
         assert depths == {1}
     best = min(trials, key=lambda t: t["ms"])
     assert tuple(best["schedule"]) == tuple(chosen)
+    # every candidate is a schedule program that compiles to its knobs
+    for t in trials:
+        assert tuple(hx.compile_schedule(t["text"])) == tuple(t["schedule"]), t
     assert all(t["ms"] > 0 for t in trials)
     o = oracle.edge_detect(img, ks, sigma, THETA, stages=True)
     r = parity.compare_mask(mask, o, THETA)
