@@ -5,7 +5,7 @@ and the benchmark's CPU-baseline leg may import this package.  It imports
 nothing from paper_2503_10855_amd; the product path never imports it.
 
 The stage definitions (O1..O8) and the reading of the paper they rest on are
-in oracle/hxo.h.
+in oracle/hxo.h; SRAD's (S1..S3) in oracle/hxo_srad.h.
 """
 import ctypes
 import os
@@ -47,9 +47,15 @@ def lib():
             ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int32,
             ctypes.c_double, ctypes.c_double, ctypes.POINTER(_u8p),
             ctypes.POINTER(_i64), _f64p, ctypes.c_int32]
+        L.hxo_srad_stats.argtypes = [_f64p, _i64, _i64, _f64p, _f64p, _f64p]
+        L.hxo_srad_coeff.argtypes = [_f64p, _i64, _i64, ctypes.c_double, _f64p]
+        L.hxo_srad_update.argtypes = [_f64p, _f64p, _i64, _i64, ctypes.c_double, _f64p]
+        L.hxo_srad.argtypes = [_f32p, _i64, _i64, _i64, ctypes.c_int32, ctypes.c_double,
+                               _f64p, _f64p]
         for name in ("hxo_gauss_weights", "hxo_blur", "hxo_laplacian",
                      "hxo_zero_crossing", "hxo_sobel", "hxo_threshold",
-                     "hxo_edge_detect", "hxo_edge_detect_many"):
+                     "hxo_edge_detect", "hxo_edge_detect_many", "hxo_srad_stats",
+                     "hxo_srad_coeff", "hxo_srad_update", "hxo_srad"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,3 +185,48 @@ def edge_detect_many(imgs, ksize=5, sigma=1.0, theta=0.1, nthreads=1):
                                       Mk, MP, _p(Ms, _f64p), nthreads),
            "edge_detect_many")
     return masks, Ms
+
+
+# ---------------------------------------------------------------- SRAD --
+def _dense64(J):
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    if J.ndim != 2:
+        raise TypeError("SRAD oracle input must be 2-D")
+    return J
+
+
+def srad_stats(J):
+    """S1 on a 2-D array: (q0^2, mean, var), in fp64."""
+    J = _dense64(J)
+    q, m, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().hxo_srad_stats(_p(J, _f64p), J.shape[0], J.shape[1], ctypes.byref(q),
+                                ctypes.byref(m), ctypes.byref(v)), "srad_stats")
+    return q.value, m.value, v.value
+
+
+def srad_coeff(J, q0sqr):
+    """S2: the diffusion coefficient c of every pixel."""
+    J = _dense64(J)
+    c = np.empty_like(J)
+    _check(lib().hxo_srad_coeff(_p(J, _f64p), J.shape[0], J.shape[1], q0sqr, _p(c, _f64p)),
+           "srad_coeff")
+    return c
+
+
+def srad_update(J, c, lam):
+    """S3: J + lambda/4 * D."""
+    J, c = _dense64(J), _dense64(c)
+    out = np.empty_like(J)
+    _check(lib().hxo_srad_update(_p(J, _f64p), _p(c, _f64p), J.shape[0], J.shape[1], lam,
+                                 _p(out, _f64p)), "srad_update")
+    return out
+
+
+def srad(img, niter, lam):
+    """niter SRAD iterations of an fp32 image: (J after them, q0^2 of each)."""
+    a, pitch = _img2d(img)
+    out = np.empty(a.shape, np.float64)
+    q = np.zeros(max(niter, 1), np.float64)
+    _check(lib().hxo_srad(_p(a, _f32p), a.shape[0], a.shape[1], pitch, niter, lam,
+                          _p(out, _f64p), _p(q, _f64p)), "srad")
+    return out, q[:niter]

@@ -12,11 +12,11 @@ LIB = os.path.join(HERE, "libhx_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "edge_oracle.c")
+    srcs = [os.path.join(HERE, f) for f in ("edge_oracle.c", "srad_oracle.c")]
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-pthread",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           src, "-o", tmp, "-lm"]
+           *srcs, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
