@@ -236,6 +236,27 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
  * ksize values or devices are ignored). */
 hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path);
 
+/* --------------------------------------------------------------- SRAD --
+ * The second workload (Evaluation; Use and Impact of Schedules): niter
+ * iterations of speckle reducing anisotropic diffusion on the fp32 image
+ * d_J (device, height x width, row pitch `pitch` elements), in place.  Per
+ * iteration, with the whole image as the region of interest and clamped
+ * neighbours: q0^2 = var(J) / mean(J)^2 (sums in fp64 over a three-level
+ * tree: thread, wave64 shuffles, one workgroup over the per-wave
+ * partials); c = 1 / (1 + (q^2 - q0^2) / (q0^2 (1 + q0^2))) clamped to
+ * [0, 1] (1 when q0^2 <= 0), q^2 from the pixel's four differences;
+ * J += lambda/4 (c dN + c_S dS + c dW + c_E dE).  fused != 0 keeps c in
+ * LDS (one kernel per iteration) instead of writing and re-reading a c
+ * plane; both forms give the same bits.  d_q0sqr (device, nullable)
+ * receives the niter values of q0^2.  Inputs must be finite and > 0.
+ * HX_E_INVALID for a NULL pipeline or image, a bad shape or pitch, more
+ * than max_pixels pixels, niter < 0 or lambda outside [0, 4]; nothing is
+ * enqueued then.  Scratch (a second plane, the c plane of the unfused
+ * form, the partial sums) is owned by the pipeline. */
+hx_status hx_srad(hx_pipeline* p, float* d_J, int64_t height, int64_t width,
+                  int64_t pitch, int32_t niter, float lambda, int32_t fused,
+                  double* d_q0sqr, hipStream_t stream);
+
 /* ------------------------------------------------------------ serving --
  * A request loop with continuous batching.  Requests are admitted while
  * their device buffers fit in the HBM budget, copied to the device, and

@@ -26,7 +26,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++20", "-fPIC", "-Wall",
          "-I" + CSRC, "-I" + os.path.join(ROOT, "include")]
 
 PLAIN = ["k_stages.hip", "k_sweep.hip", "k_batch.hip", "hx_api.cpp",
-         "hx_tune.hip", "hx_serve.cpp", "hx_sched.cpp"]
+         "hx_tune.hip", "hx_serve.cpp", "hx_sched.cpp", "k_srad.hip"]
 SWEEP_KS = (3, 5, 7)
 SWEEP_MODES = (0, 1, 2, 3, 4)
 

@@ -568,6 +568,10 @@ void hx_pipeline_destroy(hx_pipeline* p) {
     p->bufG2.release();
     p->bufZ.release();
     p->bufPart.release();
+    p->srad_j.release();
+    p->srad_c.release();
+    p->srad_part.release();
+    p->srad_q.release();
     if (p->slot1) (void)hipFree(p->slot1);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
@@ -695,6 +699,38 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img, float* d_B,
     b.G2 = (float*)p->bufG2.ptr;
     b.Z = (uint8_t*)p->bufZ.ptr;
     HX_TRY(launch_export_stages(a, b, d_B, d_L, d_Z, d_G, stream));
+    return HX_OK;
+}
+
+hx_status hx_srad(hx_pipeline* p, float* d_J, int64_t height, int64_t width, int64_t pitch,
+                  int32_t niter, float lambda, int32_t fused, double* d_q0sqr,
+                  hipStream_t stream) {
+    if (!p) return fail(HX_E_INVALID, "pipeline is NULL");
+    if (!d_J) return fail(HX_E_INVALID, "d_J is NULL");
+    if (height < 1 || width < 1 || pitch < width)
+        return fail(HX_E_INVALID, "bad image shape %lldx%lld or pitch %lld",
+                    (long long)height, (long long)width, (long long)pitch);
+    if (height * width > p->prm.max_pixels)
+        return fail(HX_E_INVALID, "image of %lld pixels exceeds max_pixels %lld",
+                    (long long)(height * width), (long long)p->prm.max_pixels);
+    if (niter < 0) return fail(HX_E_INVALID, "niter %d is negative", niter);
+    if (!(lambda == lambda) || lambda < 0.0f || lambda > 4.0f)
+        return fail(HX_E_INVALID, "lambda %g not in [0, 4]", (double)lambda);
+    DeviceGuard g(p->device);
+    const int64_t pb = (width + 3) & ~int64_t(3);
+    const size_t plane = (size_t)height * (size_t)pb * sizeof(float);
+    HX_TRY(p->srad_j.ensure(plane));
+    if (!fused) HX_TRY(p->srad_c.ensure(plane));
+    HX_TRY(p->srad_part.ensure((size_t)srad_tiles(height, width) * 8 * sizeof(double)));
+    HX_TRY(p->srad_q.ensure(sizeof(float)));
+    float* jb = (float*)p->srad_j.ptr;
+    HX_TRY(launch_srad(d_J, jb, pitch, pb, fused ? nullptr : (float*)p->srad_c.ptr, pb,
+                       (double*)p->srad_part.ptr, (float*)p->srad_q.ptr, d_q0sqr,
+                       (int)height, (int)width, niter, lambda, fused != 0, stream));
+    if (niter % 2 == 1)
+        HX_TRY(hipMemcpy2DAsync(d_J, (size_t)pitch * sizeof(float), jb, (size_t)pb * sizeof(float),
+                                (size_t)width * sizeof(float), (size_t)height,
+                                hipMemcpyDeviceToDevice, stream));
     return HX_OK;
 }
 

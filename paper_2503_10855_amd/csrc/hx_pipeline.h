@@ -96,6 +96,9 @@ struct hx_pipeline {
     // Per-image scratch.
     uint32_t* slot1 = nullptr;
     hx::DevBuf code1, bufB, bufL, bufG2, bufZ, bufPart;
+    // SRAD scratch: the second J plane, the c plane (unfused form), the
+    // per-wave partial sums, q0^2.
+    hx::DevBuf srad_j, srad_c, srad_part, srad_q;
 
     // Batched launches.
     static constexpr int kContexts = 6;
@@ -120,13 +123,13 @@ hx_status validate_image(const hx_pipeline* p, const hx_image* img);
 // and the autotuner).
 hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
                     const hx_schedule& s, hipStream_t stream);
-// The batched form with an explicit pass mode.
 // Pass structure of batched calls unless one is fixed: SPECULATE reads
 // the input about 1.1 times (once, plus the sampled bands) and measured
-// fastest on the 64 x 1920x1080 batch (0.34 ms per step against 0.37 ms
+// fastest on the 64 x 1920x1080 batch (0.30 ms per step against 0.36 ms
 // for RECOMPUTE and 0.46 ms for STORE).
 constexpr int kBatchPass = HX_PASS_SPECULATE;
 
+// The batched form with an explicit pass mode.
 hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
                       float* d_max, int pass_mode, hipStream_t stream);
 // Wait for a context's last launch.

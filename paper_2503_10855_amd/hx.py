@@ -81,6 +81,8 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
     "hx_serve_now": (ctypes.c_double, [_P]),
+    "hx_srad": (ctypes.c_int, [_P, _P, _i64, _i64, _i64, _i32, ctypes.c_float, _i32, _P,
+                               _P]),
     "hx_schedule_compile": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Schedule)]),
     "hx_schedule_to_text": (ctypes.c_int, [ctypes.POINTER(Schedule), ctypes.c_char_p,
                                            ctypes.c_size_t]),
@@ -262,6 +264,17 @@ class Pipeline:
             out["Z"].data_ptr(), out["G"].data_ptr(), out["M"].data_ptr(),
             _stream(stream)), "hx_edge_detect_stages")
         return out
+
+    def srad(self, J, niter, lam=0.5, fused=True, q_log=None, stream=None):
+        """niter SRAD iterations on the fp32 device tensor J (H, W), in
+        place; q_log (float64 device tensor of niter, optional) receives
+        q0^2 of each iteration."""
+        assert J.dtype == torch.float32 and J.dim() == 2 and J.stride(1) == 1
+        _check(_lib.hx_srad(self._h, J.data_ptr(), J.shape[0], J.shape[1], J.stride(0),
+                            niter, lam, 1 if fused else 0,
+                            q_log.data_ptr() if q_log is not None else None,
+                            _stream(stream)), "hx_srad")
+        return J
 
     def autotune(self, H, W, cache_path=None):
         _check(_lib.hx_autotune(self._h, H, W,

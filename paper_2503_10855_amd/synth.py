@@ -138,3 +138,15 @@ def serving_requests(n: int = 20000, pool: int = SERVING_POOL,
         x0 = int(rng.integers(0, side - w + 1))
         out.append((j, y0, x0, h, w))
     return out
+
+
+SEED_SRAD = 6
+
+
+def speckle(H: int, W: int, config_seed: int = SEED_SRAD, index: int = 0) -> np.ndarray:
+    """A positive float32 speckle image for SRAD: the piecewise-constant
+    scene of image() times multiplicative gamma(4, 1/4) noise (mean 1),
+    plus 0.05 so that every pixel is > 0."""
+    scene = image(H, W, config_seed, index, 8).astype(np.float64)
+    rng = np.random.default_rng(np.random.SeedSequence([config_seed, index, 7]))
+    return (scene * rng.gamma(4.0, 0.25, (H, W)) + 0.05).astype(np.float32)

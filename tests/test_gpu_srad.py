@@ -1,0 +1,95 @@
+"""SRAD on the GPU against the fp64 oracle.
+
+Tolerance: J is fp32 on the GPU and fp64 in the oracle.  One iteration
+rounds each pixel about 20 times in fp32 (differences, g2, l, q^2, c, the
+update), each at most 2^-24 of values that stay within max|J| in size, so
+it adds at most ~2e-6 max|J| of error per iteration; q0^2 is summed in
+fp64.  The test allows 3e-6 max|J| per iteration.  The fused and unfused
+forms must agree bit for bit, and the sum of J (conserved exactly by the
+definition) must stay within the same bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2503_10855_amd import synth
+
+pytestmark = pytest.mark.gpu
+LAM = 0.5
+
+
+@pytest.fixture(scope="module")
+def hx():
+    from paper_2503_10855_amd import hx as mod
+    return mod
+
+
+SHAPES = [(1, 1), (1, 70), (70, 1), (2, 3), (31, 65), (64, 64), (100, 257), (300, 513)]
+
+
+def run(p, img, niter, fused, pad=0):
+    H, W = img.shape
+    buf = torch.zeros((H, W + pad), dtype=torch.float32, device="cuda")
+    J = buf[:, :W]
+    J.copy_(torch.from_numpy(img).cuda())
+    q = torch.zeros(max(niter, 1), dtype=torch.float64, device="cuda")
+    p.srad(J, niter, LAM, fused=fused, q_log=q)
+    torch.cuda.synchronize()
+    return J.cpu().numpy(), q.cpu().numpy()[:niter], buf.cpu().numpy()
+
+
+@pytest.mark.parametrize("niter", [1, 4, 10])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_srad_matches_oracle(hx, shape, niter):
+    img = synth.speckle(*shape, index=shape[0] * 7 + shape[1])
+    ref, qref = oracle.srad(img, niter, LAM)
+    with hx.Pipeline(max_pixels=1 << 22) as p:
+        print(f"srad {shape} niter={niter}", flush=True)
+        Jf, qf, _ = run(p, img, niter, True)
+        Ju, qu, _ = run(p, img, niter, False)
+    assert np.array_equal(Jf, Ju) and np.array_equal(qf, qu)
+    scale = np.abs(ref).max()
+    err = np.abs(Jf.astype(np.float64) - ref).max()
+    print(f"  max |J - J_ora| = {err:.3e} ({err / scale:.3e} of max|J|)", flush=True)
+    assert err <= 3e-6 * niter * scale, (err, scale)
+    assert np.all(np.abs(qf - qref) <= 1e-5 * np.abs(qref) + 1e-12), (qf, qref)
+    s0 = img.astype(np.float64).sum()
+    assert abs(Jf.astype(np.float64).sum() - s0) <= 3e-6 * niter * abs(s0)
+
+
+def test_srad_zero_iterations_and_pitch(hx):
+    img = synth.speckle(45, 77, index=3)
+    with hx.Pipeline(max_pixels=1 << 22) as p:
+        J0, _, _ = run(p, img, 0, True)
+        assert np.array_equal(J0, img)
+        Jp, qp, buf = run(p, img, 3, True, pad=5)   # pitch 82, odd niter: copied back
+        Jd, qd, _ = run(p, img, 3, True)
+    assert np.array_equal(Jp, Jd) and np.array_equal(qp, qd)
+    assert np.all(buf[:, 77:] == 0)                 # the padding is untouched
+
+
+def test_srad_flat_image_is_unchanged(hx):
+    img = np.full((33, 40), 0.7, np.float32)
+    with hx.Pipeline(max_pixels=1 << 22) as p:
+        J, q, _ = run(p, img, 5, True)
+    assert np.array_equal(J, img) and np.all(np.abs(q) <= 1e-12)
+
+
+def test_srad_rejects_bad_arguments(hx):
+    import ctypes
+    lib = hx.raw()
+    with hx.Pipeline(max_pixels=1000) as p:
+        J = torch.ones((10, 10), device="cuda")
+        ptr = J.data_ptr()
+        assert lib.hx_srad(p.handle, None, 10, 10, 10, 1, ctypes.c_float(0.5), 1, None,
+                           None) == hx.HX_E_INVALID
+        assert lib.hx_srad(p.handle, ptr, 10, 10, 9, 1, ctypes.c_float(0.5), 1, None,
+                           None) == hx.HX_E_INVALID
+        assert lib.hx_srad(p.handle, ptr, 100, 100, 100, 1, ctypes.c_float(0.5), 1, None,
+                           None) == hx.HX_E_INVALID
+        assert lib.hx_srad(p.handle, ptr, 10, 10, 10, -1, ctypes.c_float(0.5), 1, None,
+                           None) == hx.HX_E_INVALID
+        assert lib.hx_srad(p.handle, ptr, 10, 10, 10, 1, ctypes.c_float(5.0), 1, None,
+                           None) == hx.HX_E_INVALID
+        torch.cuda.synchronize()
+        assert torch.all(J == 1)
