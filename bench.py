@@ -45,23 +45,27 @@ def workloads():
             "single-8192-k7": synth.large_8192, "single-256": synth.single_256}
 
 
-def source_hash():
+SRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_srad_4096.json")
+SRAD_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in ("k_srad.hip", "hx_kernels.h")]
+
+
+def source_hash(sources=None):
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in sources or SWEEP_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, pixels):
+def measured_traffic(kernel, pixels, path=TRAFFIC_FILE, sources=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when absent or taken on different kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash() or t.get("pixels") != pixels:
+    if t.get("source_hash") != source_hash(sources) or t.get("pixels") != pixels:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -135,18 +139,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="batch", choices=("batch", "serve", "reduce", "tune"),
+    ap.add_argument("--mode", default="batch",
+                    choices=("batch", "serve", "reduce", "tune", "srad"),
                     help="batch: the batched step (default); serve: the continuous-"
                          "batching server under Poisson arrivals; reduce: the "
                          "max-reduction ablation on the unfused per-image form; tune: "
                          "the autotuner's measurement of every schedule on the "
-                         "workload's first image shape")
+                         "workload's first image shape; srad: the second workload")
     ap.add_argument("--workload", default="batch-64x1080p", choices=sorted(workloads()))
     ap.add_argument("--requests", type=int, default=20000, help="serve: requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
     ap.add_argument("--budget-mb", type=int, default=32 * 1024, help="serve: HBM budget")
     ap.add_argument("--streams", type=int, default=4, help="serve: compute streams")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
+    ap.add_argument("--srad-side", type=int, default=4096, help="srad: image side")
+    ap.add_argument("--srad-iters", type=int, default=100, help="srad: iterations per step")
     ap.add_argument("--images-reduce", type=int, default=8,
                     help="reduce: 1920x1080 images per step")
     ap.add_argument("--pass-mode", type=int, default=0, choices=(0, 1, 2, 3),
@@ -181,6 +188,8 @@ def main():
         return run_reduce(args, hx)
     if args.mode == "tune":
         return run_tune(args, hx)
+    if args.mode == "srad":
+        return run_srad(args, hx)
 
     wl = workloads()[args.workload]()
     images = [wl.image(i) for i in range(len(wl.sizes))]
@@ -308,19 +317,27 @@ def main():
     ms_copy, _ = timed(lambda: cbuf.copy_(ca), 10, 2, sync)
     line["copy_gbs"] = round(2 * cb / (ms_copy * 1e-3) / 1e9, 1)
     del ca, cbuf
-    if args.calib_copy:
-        nbytes = args.calib_copy << 20
-        a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        sync()
-        for _ in range(3):
-            b.copy_(a)
-        sync()
-        line["calib_copy_bytes"] = nbytes
+    calib_copy(args, line)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, images)
         line["cpu_tuned"] = cpu_tuned(wl, images)
     print(json.dumps(line), flush=True)
+
+
+def calib_copy(args, line):
+    """With --calib-copy MIB: three device copies of that size, whose
+    FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes."""
+    if not args.calib_copy:
+        return
+    import torch
+    nbytes = args.calib_copy << 20
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    line["calib_copy_bytes"] = nbytes
 
 
 def percentiles(v, qs=(50, 99)):
@@ -472,6 +489,73 @@ def run_reduce(args, hx):
             "config": {"workload": wl.name, "images": len(imgs), "pixels": wl.pixels,
                        "schedule": "64x16 tiles, fusion depth 1"},
             "variants": out}
+    print(json.dumps(line), flush=True)
+
+
+SRAD_BYTES_PER_PX = 8.0   # fused: J read once and written once per iteration
+
+
+def run_srad(args, hx):
+    """SRAD on one 4096x4096 speckle image, 100 iterations per step: the
+    fused form (timed) and the unfused form, the oracle on the same work.
+    A step restores the input (a device copy, timed separately and
+    subtracted); the per-launch time of the fused kernel is the step's time
+    less that of a zero-iteration step (copy + the initial sums), over the
+    iterations."""
+    import torch
+    from paper_2503_10855_amd import synth
+
+    H = W = args.srad_side
+    niter = args.srad_iters
+    lam = 0.5
+    img = synth.speckle(H, W)
+    J0 = torch.from_numpy(img).cuda()
+    J = torch.empty_like(J0)
+    sync = torch.cuda.synchronize
+    out = {}
+    with hx.Pipeline(max_pixels=H * W) as p:
+        for fused in (True, False):
+            def run(n):
+                J.copy_(J0)
+                p.srad(J, n, lam, fused=fused)
+            ms_zero, _ = timed(lambda: run(0), args.steps, args.warmup, sync)
+            ms_full, _ = timed(lambda: run(niter), args.steps, args.warmup, sync)
+            out["fused" if fused else "unfused"] = (ms_full, (ms_full - ms_zero) / niter,
+                                                    J.clone())
+        ms_copy, _ = timed(lambda: J.copy_(J0), args.steps, args.warmup, sync)
+    same = bool(torch.equal(out["fused"][2], out["unfused"][2]))
+    ms_step = out["fused"][0] - ms_copy
+    ms_launch = out["fused"][1]
+    mpx_it = H * W * niter / (ms_step * 1e-3) / 1e6
+    achieved = SRAD_BYTES_PER_PX * H * W / (ms_launch * 1e-3) / 1e9
+    traffic = measured_traffic("k_srad_sweep<0>", H * W, SRAD_TRAFFIC_FILE, SRAD_SOURCES)
+    line = {"metric": "SRAD Mpixel-iterations/s", "value": round(mpx_it, 1),
+            "unit": "Mpixel*iter/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic", "vs_baseline": None,
+            "config": {"workload": f"srad-{H}x{W}-{niter}iter", "lambda": lam,
+                       "form": "fused (c in registers)"},
+            "ms_per_step": round(ms_step, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "kernel": "k_srad_sweep<0>", "ms_per_launch": round(ms_launch, 5),
+                         "bytes_per_px": SRAD_BYTES_PER_PX},
+            "copy_gbs": round(2 * 4 * H * W / (ms_copy * 1e-3) / 1e9, 1),
+            "unfused_ms_per_iteration": round(out["unfused"][1], 5),
+            "fused_over_unfused": round(out["unfused"][1] / ms_launch, 2),
+            "fused_equals_unfused": same}
+    if not args.no_cpu:
+        import oracle
+        # The oracle runs the whole workload (about 10 s on one core).
+        t0 = time.perf_counter()
+        oracle.srad(img, niter, lam)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(H * W * niter / dt / 1e6, 2),
+                                "unit": "Mpixel*iter/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the whole workload ({H}x{W}, {niter} "
+                                          f"iterations), {dt:.2f} s"}
+    calib_copy(args, line)
     print(json.dumps(line), flush=True)
 
 

@@ -242,12 +242,14 @@ hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path);
  * d_J (device, height x width, row pitch `pitch` elements), in place.  Per
  * iteration, with the whole image as the region of interest and clamped
  * neighbours: q0^2 = var(J) / mean(J)^2 (sums in fp64 over a three-level
- * tree: thread, wave64 shuffles, one workgroup over the per-wave
- * partials); c = 1 / (1 + (q^2 - q0^2) / (q0^2 (1 + q0^2))) clamped to
- * [0, 1] (1 when q0^2 <= 0), q^2 from the pixel's four differences;
- * J += lambda/4 (c dN + c_S dS + c dW + c_E dE).  fused != 0 keeps c in
- * LDS (one kernel per iteration) instead of writing and re-reading a c
- * plane; both forms give the same bits.  d_q0sqr (device, nullable)
+ * tree: lane, wave64 shuffles + the workgroup's waves, all workgroups'
+ * pairs folded at the start of the next kernel); c = 1 / (1 + (q^2 -
+ * q0^2) / (q0^2 (1 + q0^2))) clamped to [0, 1] (1 when q0^2 <= 0), q^2
+ * from the pixel's four differences; J += lambda/4 (c dN + c_S dS + c dW
+ * + c_E dE).  fused != 0 computes c in registers one row ahead of the
+ * update (one kernel per iteration, 8 B/px of HBM traffic) instead of
+ * writing and re-reading a c plane (two kernels, 20 B/px); both forms
+ * give the same bits.  d_q0sqr (device, nullable)
  * receives the niter values of q0^2.  Inputs must be finite and > 0.
  * HX_E_INVALID for a NULL pipeline or image, a bad shape or pitch, more
  * than max_pixels pixels, niter < 0 or lambda outside [0, 4]; nothing is

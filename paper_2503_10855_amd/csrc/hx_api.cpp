@@ -571,7 +571,6 @@ void hx_pipeline_destroy(hx_pipeline* p) {
     p->srad_j.release();
     p->srad_c.release();
     p->srad_part.release();
-    p->srad_q.release();
     if (p->slot1) (void)hipFree(p->slot1);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
@@ -721,11 +720,10 @@ hx_status hx_srad(hx_pipeline* p, float* d_J, int64_t height, int64_t width, int
     const size_t plane = (size_t)height * (size_t)pb * sizeof(float);
     HX_TRY(p->srad_j.ensure(plane));
     if (!fused) HX_TRY(p->srad_c.ensure(plane));
-    HX_TRY(p->srad_part.ensure((size_t)srad_tiles(height, width) * 8 * sizeof(double)));
-    HX_TRY(p->srad_q.ensure(sizeof(float)));
+    HX_TRY(p->srad_part.ensure((size_t)srad_blocks(height, width) * 4 * sizeof(double)));
     float* jb = (float*)p->srad_j.ptr;
     HX_TRY(launch_srad(d_J, jb, pitch, pb, fused ? nullptr : (float*)p->srad_c.ptr, pb,
-                       (double*)p->srad_part.ptr, (float*)p->srad_q.ptr, d_q0sqr,
+                       (double*)p->srad_part.ptr, d_q0sqr,
                        (int)height, (int)width, niter, lambda, fused != 0, stream));
     if (niter % 2 == 1)
         HX_TRY(hipMemcpy2DAsync(d_J, (size_t)pitch * sizeof(float), jb, (size_t)pb * sizeof(float),

@@ -98,7 +98,7 @@ struct hx_pipeline {
     hx::DevBuf code1, bufB, bufL, bufG2, bufZ, bufPart;
     // SRAD scratch: the second J plane, the c plane (unfused form), the
     // per-wave partial sums, q0^2.
-    hx::DevBuf srad_j, srad_c, srad_part, srad_q;
+    hx::DevBuf srad_j, srad_c, srad_part;
 
     // Batched launches.
     static constexpr int kContexts = 6;

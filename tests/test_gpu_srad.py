@@ -24,7 +24,10 @@ def hx():
     return mod
 
 
-SHAPES = [(1, 1), (1, 70), (70, 1), (2, 3), (31, 65), (64, 64), (100, 257), (300, 513)]
+# Shapes span one and several 256-column strips and 32-row bands, with a
+# ragged last strip and band, exactly one full strip, and full strips only.
+SHAPES = [(1, 1), (1, 70), (70, 1), (2, 3), (31, 65), (64, 64), (100, 257), (300, 513),
+          (33, 256), (70, 1024), (40, 1030)]
 
 
 def run(p, img, niter, fused, pad=0):
@@ -66,6 +69,18 @@ def test_srad_zero_iterations_and_pitch(hx):
         Jd, qd, _ = run(p, img, 3, True)
     assert np.array_equal(Jp, Jd) and np.array_equal(qp, qd)
     assert np.all(buf[:, 77:] == 0)                 # the padding is untouched
+
+
+def test_srad_unaligned_pitch_matches_dense(hx):
+    """Full strips read with 16-byte loads on a dense 600-wide image and
+    with element loads at pitch 603: the same bits."""
+    img = synth.speckle(50, 600, index=4)
+    with hx.Pipeline(max_pixels=1 << 22) as p:
+        for fused in (True, False):
+            Jp, qp, buf = run(p, img, 4, fused, pad=3)
+            Jd, qd, _ = run(p, img, 4, fused)
+            assert np.array_equal(Jp, Jd) and np.array_equal(qp, qd)
+            assert np.all(buf[:, 600:] == 0)
 
 
 def test_srad_flat_image_is_unchanged(hx):
