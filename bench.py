@@ -46,7 +46,7 @@ def workloads():
 
 
 SRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_srad_4096.json")
-SRAD_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in ("k_srad.hip", "hx_kernels.h")]
+SRAD_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in ("k_srad.hip", "srad_kernels.h")]
 
 
 def source_hash(sources=None):

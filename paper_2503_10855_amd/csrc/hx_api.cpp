@@ -15,6 +15,7 @@
 #include "../../include/hx.h"
 #include "hx_kernels.h"
 #include "hx_pipeline.h"
+#include "srad_kernels.h"
 
 namespace hx {
 

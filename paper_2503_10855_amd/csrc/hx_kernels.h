@@ -105,19 +105,6 @@ hipError_t launch_export_stages(const ImgArgs& a, const StageBufs& b,
                                 float* dB, float* dL, uint8_t* dZ, float* dG,
                                 hipStream_t s);
 
-// ---- SRAD ------------------------------------------------------------
-// Workgroups of one SRAD launch over an H x W image (4 sweep items of 256
-// columns x 32 rows each); the partial-sum buffer holds 4 doubles per
-// workgroup (two halves of one pair each).
-int64_t srad_blocks(int64_t H, int64_t W);
-// niter iterations on J (pitch pj): iteration k reads one of J / Jb and
-// writes the other, starting from J (so an odd niter ends in Jb).  cbuf
-// (pitch pc) is the unfused form's c plane; q_log (nullable) receives
-// niter doubles.
-hipError_t launch_srad(const float* J, float* Jb, int64_t pj, int64_t pb, float* cbuf,
-                       int64_t pc, double* partials, double* q_log, int H, int W,
-                       int niter, float lambda, bool fused, hipStream_t s);
-
 // ---- batched launch ----------------------------------------------------
 // Device descriptor table of one batched call: BatchHeader, then n_images
 // ImgArgs, then n_items1 pass-1 items, then n_items2 pass-2 items.

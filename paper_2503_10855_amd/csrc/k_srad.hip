@@ -32,8 +32,7 @@
 // the same bits for both forms and every run.
 #include <hip/hip_runtime.h>
 
-#include "../../include/hx.h"
-#include "hx_kernels.h"
+#include "srad_kernels.h"
 
 namespace hx {
 namespace {
