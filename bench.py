@@ -42,7 +42,8 @@ SWEEP_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in
 def workloads():
     from paper_2503_10855_amd import synth
     return {"batch-64x1080p": synth.batch_1080p, "uneven-512": synth.uneven_512,
-            "single-8192-k7": synth.large_8192, "single-256": synth.single_256}
+            "single-8192-k7": synth.large_8192, "single-256": synth.single_256,
+            "band-1024x8192-k7": synth.band_8192}
 
 
 SRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_srad_4096.json")
@@ -92,10 +93,32 @@ def cpu_baseline(wl, images, budget_s=12.0):
         oracle.edge_detect_many(sample, wl.ksize, wl.sigma, wl.theta, nthreads=threads)
     dt = time.perf_counter() - t0
     px = reps * sum(a.shape[0] * a.shape[1] for a in sample)
+    px0 = images[0].shape[0] * images[0].shape[1]
     return {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": min(threads, n),
             "kind": "oracle",
             "sample": f"{reps} passes over {n} of {len(images)} images of the workload, "
-                      f"one image per thread, fp64 C oracle, {dt:.2f} s wall"}
+                      f"one image per thread, fp64 C oracle, {dt:.2f} s wall",
+            "one_core_value": round(px0 / one / 1e6, 3),
+            "one_core_sample": f"image 0 alone on one core, {one:.3f} s",
+            "host": host_info()}
+
+
+def host_info():
+    """The host's CPU model and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
 
 
 def cpu_tuned(wl, images, budget_s=5.0):
@@ -114,6 +137,7 @@ def cpu_tuned(wl, images, budget_s=5.0):
     px = reps * sum(a.shape[0] * a.shape[1] for a in images)
     return {"value": round(px / dt / 1e6, 1), "unit": "Mpixel/s", "cores": threads,
             "kind": "tuned fp32 C++ (bands of 128 rows over std::threads)",
+            "host": host_info(),
             "sample": f"{reps} passes over the {len(images)} images, {dt:.2f} s wall"}
 
 
@@ -553,6 +577,7 @@ def run_srad(args, hx):
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": round(H * W * niter / dt / 1e6, 2),
                                 "unit": "Mpixel*iter/s", "cores": 1, "kind": "oracle",
+                                "host": host_info(),
                                 "sample": f"the whole workload ({H}x{W}, {niter} "
                                           f"iterations), {dt:.2f} s"}
     calib_copy(args, line)

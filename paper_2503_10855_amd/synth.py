@@ -97,6 +97,28 @@ def large_8192() -> Workload:
                     64, 7, 1.5)
 
 
+@dataclass(frozen=True)
+class BandWorkload(Workload):
+    """Rows [row0, row0 + H) of one larger image of size src_size: one
+    GPU's row band of it, halo rows included."""
+    src_size: tuple = (0, 0)
+    row0: int = 0
+
+    def image(self, i: int) -> np.ndarray:
+        h, w = self.sizes[i]
+        full = image(self.src_size[0], self.src_size[1], self.seed, 0, self.n_rect)
+        return np.ascontiguousarray(full[self.row0:self.row0 + h, :w])
+
+
+def band_8192(gpus: int = 8) -> Workload:
+    """One GPU's share of the 8192x8192 k7 image split into row bands over
+    `gpus` GPUs: the fourth band of 8192/gpus rows with the 5 halo rows
+    (blur radius 3 + 2) it needs above and below."""
+    rows, halo = 8192 // gpus, 5
+    return BandWorkload(f"band-{rows}x8192-of-8192x8192-k7", ((rows + 2 * halo, 8192),),
+                        SEED_LARGE_8192, 64, 7, 1.5, 0.1, (8192, 8192), 3 * rows - halo)
+
+
 def uneven_512(n: int = 512) -> Workload:
     """n images with each side log-uniform in [64, 2048], k5 sigma 1.0."""
     sizes = tuple(log_uniform_sizes(n, 64, 2048, SEED_UNEVEN_512))
