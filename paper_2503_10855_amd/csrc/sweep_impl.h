@@ -308,9 +308,13 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                     // Z needs only the sign of L: whether the 3x3 window
                     // holds an L > 0 (its max is > 0) and whether it holds
                     // only L > 0 (its min is > 0).  Kept as bits, C per row.
+                    // l > 0 exactly when its bits, read as a signed
+                    // integer, are >= 1 (-0 reads as INT_MIN): clamping
+                    // them to [0, 1] gives the bit without a compare.
                     uint32_t sg = 0;
 #pragma unroll
-                    for (int e = 0; e < C; ++e) sg |= (l[e] > 0.0f) ? (1u << e) : 0u;
+                    for (int e = 0; e < C; ++e)
+                        sg |= (uint32_t)min(max(__float_as_int(l[e]), 0), 1) << e;
                     const uint32_t sl = (uint32_t)__builtin_amdgcn_mov_dpp(
                         (int)sg, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
                     const uint32_t sr = (uint32_t)__builtin_amdgcn_mov_dpp(
@@ -333,44 +337,50 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                             const uint32_t any = hz[J2] | hz[J1] | hz[J];
                             const uint32_t all = hz[J2] & hz[J1] & hz[J];
                             const uint32_t zb = any & ~(all >> 8) & CM;
-                            bool z[C];
-#pragma unroll
-                            for (int e = 0; e < C; ++e) z[e] = (zb >> e) & 1u;
                             if constexpr (MODE == SM_STORE) {
                                 float code[C];
 #pragma unroll
-                                for (int e = 0; e < C; ++e) code[e] = pass1_code(z[e], g2d[e]);
+                                for (int e = 0; e < C; ++e)
+                                    code[e] = pass1_code((zb >> e) & 1u, g2d[e]);
                                 store_f(a.fout, vz, code);
                             } else {
+                                static_assert(C <= 4, "one mask byte per column in a word");
                                 const gptr<uint8_t> rp =
                                     as_global(a.mask) + (int64_t)vz * a.mp + cbase;
-                                uint32_t m[C];
+                                // Mask byte e (bit 8e of mw) = Z and G^2 > thr2.
+                                // G^2 > thr2 is the sign of thr2 - G^2 (exact
+                                // for finite values: the difference of two
+                                // different floats is never rounded to 0);
+                                // Z's C bits are spread one per byte by a
+                                // multiply.
+                                uint32_t gw = 0;
 #pragma unroll
                                 for (int e = 0; e < C; ++e)
-                                    m[e] = (z[e] & (g2d[e] > thr2)) ? 1u : 0u;
+                                    gw |= (__float_as_uint(thr2 - g2d[e]) >> 31) << (8 * e);
+                                const uint32_t mw = gw & ((zb * 0x00204081u) & 0x01010101u);
                                 if (!BX && (C == 4) && mask_vec) {
-                                    if (lane_out) {
-                                        uint32_t w = 0;
-#pragma unroll
-                                        for (int e = 0; e < C; ++e) w |= m[e] << (8 * e);
-                                        *(gptr<uint32_t>)rp = w;
-                                    }
+                                    if (lane_out) *(gptr<uint32_t>)rp = mw;
                                 } else {
 #pragma unroll
                                     for (int e = 0; e < C; ++e)
-                                        if (ecol[e]) rp[e] = (uint8_t)m[e];
+                                        if (ecol[e]) rp[e] = (uint8_t)((mw >> (8 * e)) & 1u);
                                 }
                                 if constexpr (MODE == SM_SPEC) {
                                     // List the lanes that set a bit in this
                                     // row, packed in lane order after the
                                     // tile's earlier entries: their C values
                                     // of G^2, and row | lane | set columns.
-                                    static_assert(C <= 4, "four set-bits per entry");
-                                    uint32_t bits = 0;
+                                    // The multiply gathers byte e's bit into
+                                    // bit 24 + e.
+                                    uint32_t bits = (mw * 0x01020408u) >> 24;
+                                    if constexpr (BX) {
+                                        uint32_t em = 0;
 #pragma unroll
-                                    for (int e = 0; e < C; ++e)
-                                        bits |= ((m[e] != 0u) & (BX ? ecol[e] : lane_out))
-                                                    ? (1u << e) : 0u;
+                                        for (int e = 0; e < C; ++e) em |= ecol[e] ? (1u << e) : 0u;
+                                        bits &= em;
+                                    } else {
+                                        bits = lane_out ? bits : 0u;
+                                    }
                                     const uint64_t bal = __ballot(bits != 0u);
                                     if (bal) {
                                         if (bits) {
