@@ -66,8 +66,9 @@ typedef struct hx_server hx_server;
  *              (G^2 where Z = 1, else -1) plus the max; pass 2 thresholds.
  *  RECOMPUTE:  pass 1 computes blur and Sobel only, for the max; pass 2
  *              recomputes every stage and writes the mask directly.
- *  SPECULATE:  pass 0 computes G^2 on sampled row bands (16 rows at the
- *              top of every max(32, min(256, H/4)) rows) for a lower
+ *  SPECULATE:  pass 0 computes G^2 on sampled row bands (8 rows at the
+ *              top of every min(clamp(H/32, 128, 256), max(H/4, 8))
+ *              rows) for a lower
  *              bound m <= max G^2 of each image; pass 1 computes every
  *              stage once, writes the mask against the threshold of m (a
  *              pixel it leaves at 0 is 0 under the true max too) and lists

@@ -8,7 +8,7 @@
 //           only; both fold the tile's G^2 maximum into the image's slot;
 //   pass 2  one item = a run of rows (STORE: code -> mask) or one sweep tile
 //           (RECOMPUTE: every stage -> mask) of one image.
-// SPECULATE adds pass 0 (one item = one 16-row sampled band tile: blur +
+// SPECULATE adds pass 0 (one item = one 8-row sampled band tile: blur +
 // Sobel -> a lower bound of the max), runs every stage in pass 1 (mask
 // against the bound's threshold, plus the list of pixels it set), and
 // re-decides only the listed pixels in pass 2 (one item = one pass-1 tile).

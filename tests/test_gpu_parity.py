@@ -135,8 +135,8 @@ def test_batched_equals_per_image(hx, ks, sigma, pass_mode):
 
 
 def weak_bound_images():
-    """Images on which the sampled bands of SPECULATE (16 rows at the top of
-    every max(32, min(256, H // 4)) rows) see a poor lower bound of the max,
+    """Images on which the sampled bands of SPECULATE (8 rows at the top of
+    every H // 4 rows for these heights) see a poor lower bound of the max,
     or none at all, so pass 1 lists many or most pixels: the strongest edge
     sits between the bands, or the bands are flat (bound 0: every pixel
     with Z = 1 and G > 0 is listed)."""
