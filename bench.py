@@ -141,6 +141,32 @@ def cpu_tuned(wl, images, budget_s=5.0):
             "sample": f"{reps} passes over the {len(images)} images, {dt:.2f} s wall"}
 
 
+def timed_streams(fns, streams, steps, warmup):
+    """Step i runs fns[i % S](streams[i % S]); the K timed steps are
+    bracketed by events on the current stream, which every stream waits on
+    at the start and waits for at the end."""
+    import torch
+    S = len(streams)
+    for i in range(warmup):
+        fns[i % S](streams[i % S])
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record(cur)
+    for st in streams:
+        st.wait_event(t0)
+    for i in range(steps):
+        fns[i % S](streams[i % S])
+    for st in streams:
+        cur.wait_stream(st)
+    t1.record(cur)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return t0.elapsed_time(t1) / steps, wall
+
+
 def timed(fn, steps, warmup, sync):
     import torch
     for _ in range(warmup):
@@ -161,8 +187,11 @@ def timed(fn, steps, warmup, sync):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 in batch mode, 20 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 20 in batch mode, 5 otherwise)")
+
     ap.add_argument("--mode", default="batch",
                     choices=("batch", "serve", "reduce", "tune", "srad"),
                     help="batch: the batched step (default); serve: the continuous-"
@@ -174,7 +203,10 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="serve: requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
     ap.add_argument("--budget-mb", type=int, default=32 * 1024, help="serve: HBM budget")
-    ap.add_argument("--streams", type=int, default=4, help="serve: compute streams")
+    ap.add_argument("--streams", type=int, default=None,
+                    help="serve: compute streams (default 4); batch: consecutive batches go "
+                         "to this many streams in turn, each with its own output buffers "
+                         "(default 3; 1: one stream)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
     ap.add_argument("--srad-side", type=int, default=4096, help="srad: image side")
     ap.add_argument("--srad-iters", type=int, default=100, help="srad: iterations per step")
@@ -190,6 +222,12 @@ def main():
                     help="also run a plain device-to-device copy of MIB MiB, three "
                          "times (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 200 if args.mode == "batch" else 20
+    if args.warmup is None:
+        args.warmup = 20 if args.mode == "batch" else 5
+    if args.streams is None:
+        args.streams = 3 if args.mode == "batch" else 4
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); "
@@ -218,8 +256,13 @@ def main():
     wl = workloads()[args.workload]()
     images = [wl.image(i) for i in range(len(wl.sizes))]
     srcs = [torch.from_numpy(a).cuda() for a in images]
-    masks = [torch.empty(s.shape, dtype=torch.uint8, device="cuda") for s in srcs]
-    dmax = torch.zeros(len(srcs), device="cuda")
+    # One output set per stream: batches in flight on different streams
+    # never share an output buffer.
+    S = max(1, args.streams)
+    mask_sets = [[torch.empty(s.shape, dtype=torch.uint8, device="cuda") for s in srcs]
+                 for _ in range(S)]
+    dmax_sets = [torch.zeros(len(srcs), device="cuda") for _ in range(S)]
+    masks, dmax = mask_sets[0], dmax_sets[0]
     pixels = wl.pixels
     sync = torch.cuda.synchronize
 
@@ -228,11 +271,17 @@ def main():
                      pass_mode=args.pass_mode) as p:
         sched = p.schedule(*wl.sizes[0])
 
-        prepared = p.prepare_batch(srcs, masks, dmax)
+        preps = [p.prepare_batch(srcs, m, d) for m, d in zip(mask_sets, dmax_sets)]
+        prepared = preps[0]
         batched = prepared.run
 
-        ms_step, wall = timed(batched, args.steps, args.warmup, sync)
+        streams = [torch.cuda.Stream() for _ in range(S)]
+        ms_step, wall = timed_streams([q.run for q in preps], streams, args.steps,
+                                      args.warmup)
+        ms_step_1s, _ = timed_streams([prepared.run], streams[:1], args.steps, args.warmup)
         p.sync()
+        same_sets = all(torch.equal(a, b) for ms in mask_sets[1:]
+                        for a, b in zip(mask_sets[0], ms))
         value = pixels / (ms_step * 1e-3) / 1e6
 
         # The same kernels launched directly with events around each one
@@ -308,6 +357,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_one_stream": round(ms_step_1s, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -315,7 +365,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "images": len(wl.sizes), "pixels": pixels,
                    "ksize": wl.ksize, "sigma": wl.sigma, "theta": wl.theta,
-                   "form": "batched graph launch",
+                   "form": f"batched graph launch, consecutive batches on {S} "
+                           f"stream{'s' if S > 1 else ''} in turn",
+                   "streams": S, "output_sets_identical": same_sets,
                    "pass_mode": {0: "batch default", 1: "store", 2: "recompute",
                                  3: "speculate"}[args.pass_mode],
                    "per_image_schedule": list(sched)},
