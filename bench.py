@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="serve: compute streams (default 4); batch: consecutive batches go "
                          "to this many streams in turn, each with its own output buffers "
-                         "(default 3; 1: one stream)")
+                         "(default 2; 1: one stream)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
     ap.add_argument("--srad-side", type=int, default=4096, help="srad: image side")
     ap.add_argument("--srad-iters", type=int, default=100, help="srad: iterations per step")
@@ -227,7 +227,7 @@ def main():
     if args.warmup is None:
         args.warmup = 20 if args.mode == "batch" else 5
     if args.streams is None:
-        args.streams = 3 if args.mode == "batch" else 4
+        args.streams = 2 if args.mode == "batch" else 4
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); "
