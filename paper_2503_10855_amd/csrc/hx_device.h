@@ -28,13 +28,6 @@ __device__ __forceinline__ float blur_chain(const float* v, const Taps& t) {
     return acc;
 }
 
-__device__ __forceinline__ float blur_chain_rt(const float* v, const Taps& t,
-                                               int k) {
-    float acc = t.g[0] * v[0];
-    for (int i = 1; i < k; ++i) acc = fmaf(t.g[i], v[i], acc);
-    return acc;
-}
-
 // Pairwise sums that both the Laplacian and the Sobel stage reuse.
 //   ew = B(x-1) + B(x+1)                      (same row)
 //   ns = B(y-1) + B(y+1)                      (same column)

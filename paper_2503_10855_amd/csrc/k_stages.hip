@@ -35,20 +35,29 @@ __device__ __forceinline__ int reps(const TileMap& m) {
     return (m.th + rows_per - 1) / rows_per;
 }
 
-__global__ __launch_bounds__(256) void k_blur(ImgArgs a, StageBufs b, Taps t,
-                                             int ks, TileMap m) {
-    const int r = ks / 2;
+// B of each pixel from its clamped KS x KS window: the horizontal chain of
+// each window row, then the vertical chain of the results (the sweeps'
+// order, so the same bits).  KS is a template argument so the window lives
+// in registers.
+template <int KS>
+__global__ __launch_bounds__(256) void k_blur(ImgArgs a, StageBufs b, Taps t, TileMap m) {
+    constexpr int r = KS / 2;
     for (int k = 0; k < reps(m); ++k) {
         int x, y;
         if (!tile_px(m, k, a.W, a.H, x, y)) continue;
-        float col[kMaxK];
-        for (int i = 0; i < ks; ++i) {
+        int xs[KS];
+#pragma unroll
+        for (int j = 0; j < KS; ++j) xs[j] = clampi(x - r + j, 0, a.W - 1);
+        float col[KS];
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
             const float* rp = a.src + (int64_t)clampi(y - r + i, 0, a.H - 1) * a.sp;
-            float row[kMaxK];
-            for (int j = 0; j < ks; ++j) row[j] = rp[clampi(x - r + j, 0, a.W - 1)];
-            col[i] = blur_chain_rt(row, t, ks);
+            float row[KS];
+#pragma unroll
+            for (int j = 0; j < KS; ++j) row[j] = rp[xs[j]];
+            col[i] = blur_chain<KS>(row, t);
         }
-        b.B[(int64_t)y * b.op + x] = blur_chain_rt(col, t, ks);
+        b.B[(int64_t)y * b.op + x] = blur_chain<KS>(col, t);
     }
 }
 
@@ -134,8 +143,16 @@ __global__ __launch_bounds__(256) void k_sobel(ImgArgs a, StageBufs b,
         mx = __builtin_fmaxf(mx, g2);
     }
     if (reduce == HX_REDUCE_TREE) {
+        // Wave maxima by shuffles, the workgroup's 4 through LDS, one
+        // device-scope atomic per workgroup (every atomic of the kernel
+        // lands on the image's one slot, so fewer is faster).
+        __shared__ float wm[4];
         mx = wave_max(mx);
-        if (lane_id() == 0) atomic_max_g2(a.slot, mx);
+        if (lane_id() == 0) wm[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomic_max_g2(a.slot, __builtin_fmaxf(__builtin_fmaxf(wm[0], wm[1]),
+                                                  __builtin_fmaxf(wm[2], wm[3])));
     }
 }
 
@@ -252,7 +269,18 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 hipError_t launch_blur(const ImgArgs& a, const StageBufs& b, const Taps& t,
                        int ks, int tw, int th, hipStream_t s) {
     const TileMap m = make_map(a, tw, th);
-    hipLaunchKernelGGL(k_blur, dim3(grid_of(m)), dim3(256), 0, s, a, b, t, ks, m);
+    const dim3 g(grid_of(m)), blk(256);
+    switch (ks) {
+        case 1: hipLaunchKernelGGL(k_blur<1>, g, blk, 0, s, a, b, t, m); break;
+        case 3: hipLaunchKernelGGL(k_blur<3>, g, blk, 0, s, a, b, t, m); break;
+        case 5: hipLaunchKernelGGL(k_blur<5>, g, blk, 0, s, a, b, t, m); break;
+        case 7: hipLaunchKernelGGL(k_blur<7>, g, blk, 0, s, a, b, t, m); break;
+        case 9: hipLaunchKernelGGL(k_blur<9>, g, blk, 0, s, a, b, t, m); break;
+        case 11: hipLaunchKernelGGL(k_blur<11>, g, blk, 0, s, a, b, t, m); break;
+        case 13: hipLaunchKernelGGL(k_blur<13>, g, blk, 0, s, a, b, t, m); break;
+        case 15: hipLaunchKernelGGL(k_blur<15>, g, blk, 0, s, a, b, t, m); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
