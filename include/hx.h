@@ -51,7 +51,7 @@ typedef enum {
     HX_E_INVALID = 1,      /* bad argument; nothing enqueued            */
     HX_E_NOMEM = 2,        /* device or pinned host allocation failed   */
     HX_E_HIP = 3,          /* a HIP runtime call failed                 */
-    HX_E_UNSUPPORTED = 4,  /* valid request this build cannot run       */
+    HX_E_UNSUPPORTED = 4,  /* valid request the library does not support */
     HX_E_BUSY = 5,         /* server: request would never fit budget    */
     HX_E_PENDING = 6,      /* server: ticket not finished yet           */
     HX_E_NOT_FOUND = 7     /* server: unknown or already-collected id   */
