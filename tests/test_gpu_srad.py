@@ -108,3 +108,36 @@ def test_srad_rejects_bad_arguments(hx):
                            None) == hx.HX_E_INVALID
         torch.cuda.synchronize()
         assert torch.all(J == 1)
+
+
+def test_srad_random_shapes_pitches_and_lambdas(hx):
+    """Seeded random sides in [1, 700], 0-7 floats of row padding, lambda in
+    (0, 1] and 1-7 iterations: fused == unfused bit for bit, both within
+    the tolerance of the oracle."""
+    rng = np.random.default_rng(np.random.SeedSequence([6, 77]))
+    with hx.Pipeline(max_pixels=1 << 22) as p:
+        for i in range(12):
+            h = int(round(np.exp(rng.uniform(0, np.log(700)))))
+            w = int(round(np.exp(rng.uniform(0, np.log(700)))))
+            pad = int(rng.integers(0, 8))
+            lam = float(rng.uniform(0.05, 1.0))
+            niter = int(rng.integers(1, 8))
+            img = synth.speckle(h, w, index=100 + i)
+            ref, qref = oracle.srad(img, niter, lam)
+            print(f"srad random {h}x{w} pad {pad} lambda {lam:.3f} niter {niter}", flush=True)
+            out = {}
+            for fused in (True, False):
+                buf = torch.zeros((h, w + pad), dtype=torch.float32, device="cuda")
+                J = buf[:, :w]
+                J.copy_(torch.from_numpy(img).cuda())
+                q = torch.zeros(niter, dtype=torch.float64, device="cuda")
+                p.srad(J, niter, lam, fused=fused, q_log=q)
+                torch.cuda.synchronize()
+                out[fused] = (J.cpu().numpy(), q.cpu().numpy(), buf[:, w:].cpu().numpy())
+            assert np.array_equal(out[True][0], out[False][0])
+            assert np.array_equal(out[True][1], out[False][1])
+            assert np.all(out[True][2] == 0)
+            scale = np.abs(ref).max()
+            err = np.abs(out[True][0].astype(np.float64) - ref).max()
+            assert err <= 3e-6 * niter * scale, (h, w, err, scale)
+            assert np.all(np.abs(out[True][1] - qref) <= 1e-5 * np.abs(qref) + 1e-12)
