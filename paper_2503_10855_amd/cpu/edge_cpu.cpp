@@ -195,7 +195,13 @@ int hx_cpu_edge_detect_many(int n, const float* const* src, const int64_t* H,
             for (size_t u; (u = next.fetch_add(1)) < units.size();) body(u, t);
         };
         std::vector<std::thread> pool;
-        for (int t = 1; t < threads; ++t) pool.emplace_back(worker, t);
+        for (int t = 1; t < threads; ++t) {
+            try {
+                pool.emplace_back(worker, t);
+            } catch (...) {  // fewer threads: the others take the units
+                break;
+            }
+        }
         worker(0);
         for (auto& t : pool) t.join();
     };

@@ -61,7 +61,12 @@ void copy_rows(void* dst, size_t dst_pitch, const void* src, size_t src_pitch,
     std::vector<std::thread> pool;
     for (int64_t t = 1; t < nt; ++t) {
         const int64_t r0 = t * per, r1 = std::min(rows, r0 + per);
-        if (r0 < r1) pool.emplace_back(part, r0, r1);
+        if (r0 >= r1) continue;
+        try {
+            pool.emplace_back(part, r0, r1);
+        } catch (...) {  // no thread to be had: copy these rows here
+            part(r0, r1);
+        }
     }
     part(0, std::min(rows, per));
     for (auto& th : pool) th.join();
@@ -340,7 +345,13 @@ hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp, void* d_are
     }
     s->t0 = std::chrono::steady_clock::now();
     hx_server* raw = s.get();
-    raw->sched = std::thread(scheduler, raw);
+    try {
+        raw->sched = std::thread(scheduler, raw);
+    } catch (...) {
+        for (auto x : s->streams) (void)hipStreamDestroy(x);
+        (void)hipHostFree(s->host);
+        return fail(HX_E_NOMEM, "could not start the scheduler thread");
+    }
     *out = s.release();
     return HX_OK;
 }
