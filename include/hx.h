@@ -187,7 +187,11 @@ hx_status hx_pipeline_last_timing(hx_pipeline* p, float* ms);
 hx_status hx_schedule_compile(const char* text, hx_schedule* out);
 hx_status hx_schedule_to_text(const hx_schedule* s, char* buf, size_t len);
 
-/* Force a schedule for every later call (NULL restores automatic choice).
+/* Force a schedule for every later call (NULL restores automatic choice:
+ * the autotuned schedule of the image's shape class if there is one, else
+ * fusion depth 4, STORE, 256-column tiles of the tallest of 64, 32 or 16
+ * rows that gives every SIMD a tile, and fusion depth 1 with 64 x 16
+ * tiles for a blur size the sweeps do not cover).
  * HX_E_INVALID for knob values outside the sets documented above,
  * HX_E_UNSUPPORTED for a fused depth with ksize not in {3,5,7}. */
 hx_status hx_pipeline_set_schedule(hx_pipeline* p, const hx_schedule* s);

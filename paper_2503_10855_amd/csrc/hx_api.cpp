@@ -117,7 +117,15 @@ hx_schedule choose_schedule(const hx_pipeline* p, int64_t H, int64_t W) {
     if (it != p->tuned.end()) {
         s = it->second;
     } else if (fused_ks(p->prm.ksize)) {
-        s = hx_schedule{256, 64, 4, HX_PASS_STORE, HX_REDUCE_TREE};
+        // Untuned: 256-column tiles, one wave each, and the tallest tile of
+        // 64, 32 or 16 rows that still gives every SIMD a wave (taller
+        // tiles re-read fewer halo rows; a 1080p image in 64-row tiles
+        // would leave seven SIMDs in eight idle).
+        const int64_t simds = 4 * (int64_t)(p->cu_count > 0 ? p->cu_count : 256);
+        const int64_t strips = (W + 239) / 240;
+        int th = 64;
+        while (th > 16 && strips * ((H + th - 1) / th) < simds) th /= 2;
+        s = hx_schedule{256, th, 4, HX_PASS_STORE, HX_REDUCE_TREE};
     } else {
         s = hx_schedule{64, 16, 1, HX_PASS_STORE, HX_REDUCE_TREE};
     }
