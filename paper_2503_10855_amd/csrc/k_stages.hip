@@ -117,6 +117,57 @@ __global__ __launch_bounds__(256) void k_lap_zero_cross(ImgArgs a, StageBufs b,
     }
 }
 
+// Depth 2's second kernel for 64 x 16 output tiles: B of the tile and a
+// 2-pixel halo is staged in LDS once, L of the tile and a 1-pixel halo is
+// computed into LDS once per pixel, and Z reads its 3 x 3 window from LDS
+// (instead of 9 Laplacians of 5 global loads each per pixel).  Every LDS
+// cell holds the stage's value at the clamped image position, so the same
+// operands reach lap_from and zero_cross as in k_lap_zero_cross: the same
+// bits.
+constexpr int kLzW = 64, kLzH = 16;
+__global__ __launch_bounds__(256) void k_lap_zero_cross_lds(ImgArgs a, StageBufs b,
+                                                           TileMap m) {
+    constexpr int BW = kLzW + 4, BH = kLzH + 4, LW = kLzW + 2, LH = kLzH + 2;
+    __shared__ float sB[BH][BW];
+    __shared__ float sL[LH][LW];
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int x0 = (bid % m.tiles_x) * kLzW, y0 = (bid / m.tiles_x) * kLzH;
+    const int H = a.H, W = a.W;
+    // B at clamped (y0 - 2 + r, x0 - 2 + c).
+    for (int i = threadIdx.x; i < BH * BW; i += 256) {
+        const int r = i / BW, c = i - r * BW;
+        sB[r][c] = b.B[(int64_t)clampi(y0 - 2 + r, 0, H - 1) * b.op + clampi(x0 - 2 + c, 0, W - 1)];
+    }
+    __syncthreads();
+    // L at clamped (y0 - 1 + r, x0 - 1 + c); its B neighbours at clamped
+    // positions, found in sB at (image row - (y0 - 2), image col - (x0 - 2)).
+    for (int i = threadIdx.x; i < LH * LW; i += 256) {
+        const int r = i / LW, c = i - r * LW;
+        const int y = clampi(y0 - 1 + r, 0, H - 1), x = clampi(x0 - 1 + c, 0, W - 1);
+        const int ry = y - (y0 - 2), rx = x - (x0 - 2);
+        const int rn = clampi(y - 1, 0, H - 1) - (y0 - 2), rs = clampi(y + 1, 0, H - 1) - (y0 - 2);
+        const int cw = clampi(x - 1, 0, W - 1) - (x0 - 2), ce = clampi(x + 1, 0, W - 1) - (x0 - 2);
+        const float ns = sB[rn][rx] + sB[rs][rx];
+        const float ew = sB[ry][cw] + sB[ry][ce];
+        sL[r][c] = lap_from(ns, ew, sB[ry][rx]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kLzH * kLzW; i += 256) {
+        const int ly = i / kLzW, lx = i - ly * kLzW;
+        const int y = y0 + ly, x = x0 + lx;
+        if (y >= H || x >= W) continue;
+        float mx = -__builtin_inff(), mn = __builtin_inff();
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const float v = sL[clampi(y + dy, 0, H - 1) - (y0 - 1)]
+                                  [clampi(x + dx, 0, W - 1) - (x0 - 1)];
+                mx = __builtin_fmaxf(mx, v);
+                mn = __builtin_fminf(mn, v);
+            }
+        b.Z[(int64_t)y * b.op + x] = zero_cross(mx, mn) ? 1 : 0;
+    }
+}
+
 __device__ __forceinline__ float g2_at(const float* B, int64_t op, int y,
                                        int x, int H, int W) {
     float dxr[3], syr[3];
@@ -301,7 +352,10 @@ hipError_t launch_zero_cross(const ImgArgs& a, const StageBufs& b,
 hipError_t launch_lap_zero_cross(const ImgArgs& a, const StageBufs& b, int tw,
                                  int th, hipStream_t s) {
     const TileMap m = make_map(a, tw, th);
-    hipLaunchKernelGGL(k_lap_zero_cross, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
+    if (tw == kLzW && th == kLzH)
+        hipLaunchKernelGGL(k_lap_zero_cross_lds, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
+    else
+        hipLaunchKernelGGL(k_lap_zero_cross, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
     return hipGetLastError();
 }
 
