@@ -144,11 +144,24 @@ def cpu_tuned(wl, images, budget_s=5.0):
 def timed_streams(fns, streams, steps, warmup):
     """Step i runs fns[i % S](streams[i % S]); the K timed steps are
     bracketed by events on the current stream, which every stream waits on
-    at the start and waits for at the end."""
+    at the start and waits for at the end.  The warm-up runs at least three
+    calls per stream whatever `warmup` says (the first builds a batch
+    context's table, the second captures its graph, the third replays it),
+    so every timed call replays a captured graph."""
     import torch
     S = len(streams)
-    for i in range(warmup):
+    for i in range(max(warmup, 3 * S)):
         fns[i % S](streams[i % S])
+    # Then keep the GPU busy for at least ~50 ms before the timed region, so
+    # that a short run is not timed while the clocks ramp up.
+    torch.cuda.synchronize()
+    t_end = time.perf_counter() + 0.05
+    i = 0
+    while time.perf_counter() < t_end:
+        for _ in range(S):
+            fns[i % S](streams[i % S])
+            i += 1
+        torch.cuda.synchronize()
     torch.cuda.synchronize()
     cur = torch.cuda.current_stream()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -216,6 +229,12 @@ def main():
                     help="batched pass structure: 0 default, 1 STORE, 2 RECOMPUTE, "
                          "3 SPECULATE")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch: skip the batch autotuner (default tile height and pass)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="batch: skip the short serving leg")
+    ap.add_argument("--serve-requests", type=int, default=4000,
+                    help="batch: requests of the serving leg (at --rate per second)")
     ap.add_argument("--no-per-image", action="store_true",
                     help="skip the per-image comparison forms")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -270,6 +289,15 @@ def main():
                      max_pixels=pixels, max_images=max(len(srcs), 1),
                      pass_mode=args.pass_mode) as p:
         sched = p.schedule(*wl.sizes[0])
+        # The batched launch's tile height and pass structure, chosen by the
+        # batch autotuner on this batch (unless a pass structure is fixed).
+        batch_sched = None
+        if not args.no_tune and not args.pass_mode:
+            t0 = time.perf_counter()
+            th, pm = p.autotune_batch(srcs, mask_sets[0])
+            batch_sched = {"tile_h": th, "pass": {1: "store", 2: "recompute",
+                                                  3: "speculate"}[pm],
+                           "tuner_s": round(time.perf_counter() - t0, 2)}
 
         preps = [p.prepare_batch(srcs, m, d) for m, d in zip(mask_sets, dmax_sets)]
         prepared = preps[0]
@@ -341,7 +369,10 @@ def main():
         p.set_schedule()
 
     # The dominant kernel is the longer of the two passes.
-    pm = args.pass_mode or BATCH_DEFAULT_PASS
+    if batch_sched:
+        pm = {"store": 1, "recompute": 2, "speculate": 3}[batch_sched["pass"]]
+    else:
+        pm = args.pass_mode or BATCH_DEFAULT_PASS
     dom = 1 if ms_p1 >= ms_p2 else 2
     ms_dom = ms_p1 if dom == 1 else ms_p2
     bpp = KERNEL_BYTES_PER_PX[pm][dom]
@@ -370,6 +401,7 @@ def main():
                    "streams": S, "output_sets_identical": same_sets,
                    "pass_mode": {0: "batch default", 1: "store", 2: "recompute",
                                  3: "speculate"}[args.pass_mode],
+                   "batch_schedule": batch_sched,
                    "per_image_schedule": list(sched)},
         "roofline": {"kernel": kname, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -394,6 +426,13 @@ def main():
     line["copy_gbs"] = round(2 * cb / (ms_copy * 1e-3) / 1e9, 1)
     del ca, cbuf
     calib_copy(args, line)
+    if not args.no_serve:
+        # A short serving leg: continuous batching of Poisson arrivals, the
+        # latency percentiles at that rate beside the batch throughput.
+        del srcs, mask_sets, dmax_sets
+        torch.cuda.empty_cache()
+        line["serve"] = serve_leg(hx, args.serve_requests, args.rate, args.budget_mb,
+                                  4, args.max_batch, pool_n=4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, images)
         line["cpu_tuned"] = cpu_tuned(wl, images)
@@ -421,37 +460,44 @@ def percentiles(v, qs=(50, 99)):
     return {f"p{q}": round(float(np.percentile(v, q)) * 1e3, 4) for q in qs}
 
 
-def run_serve(args, hx):
-    """Continuous batching: requests (crops of a pool of 4096x4096 images,
-    sides log-uniform in [64, 4096]) arrive as a Poisson process and are
-    submitted at their scheduled times; latency runs from the scheduled
-    arrival until the mask is in host memory."""
+def serve_leg(hx, n, rate, budget_mb, streams, max_batch, pool_n=None, verbose=True):
+    """Continuous batching: n requests (crops of a pool of 4096x4096 images,
+    sides log-uniform in [64, 4096]) arrive as a Poisson process at `rate`
+    per second and are submitted at their scheduled times; latency runs from
+    the scheduled arrival until the mask is in host memory.  Returns the
+    measurements as a dict."""
     import numpy as np
     import torch
     from paper_2503_10855_amd import synth
 
-    n = args.requests
-    print(f"serve: generating the request pool ({synth.SERVING_POOL} x "
-          f"{synth.SERVING_POOL_SIDE}^2)", file=sys.stderr, flush=True)
-    pool = synth.serving_pool()
-    reqs = synth.serving_requests(n)
-    arrivals = synth.poisson_arrivals(n, args.rate)
+    pool_n = pool_n or synth.SERVING_POOL
+    if verbose:
+        print(f"serve: generating the request pool ({pool_n} x "
+              f"{synth.SERVING_POOL_SIDE}^2)", file=sys.stderr, flush=True)
+    pool = synth.serving_pool(pool_n)
+    reqs = synth.serving_requests(n, pool=pool_n)
+    arrivals = synth.poisson_arrivals(n, rate)
     views = [pool[j][y0:y0 + h, x0:x0 + w] for j, y0, x0, h, w in reqs]
     total_px = sum(h * w for *_, h, w in reqs)
-    budget = args.budget_mb << 20
-    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
-    with hx.Pipeline(ksize=5, sigma=1.0, theta=0.1, max_pixels=1 << 26,
-                     max_images=args.max_batch) as p:
-        with hx.Server(p, hbm_budget=budget, streams=args.streams,
-                       max_batch=args.max_batch, arena=arena) as srv:
+    budget = budget_mb << 20
+    # A serving pipeline holds only the batched form's scratch, which counts
+    # against the budget; the arena takes the rest.
+    with hx.Pipeline(ksize=5, sigma=1.0, theta=0.1, max_pixels=1 << 25,
+                     max_images=max_batch, forms=hx.FORM_BATCH,
+                     batch_contexts=streams) as p:
+        own = p.memory()[0]
+        arena = torch.empty(max(budget - own, 1 << 12), dtype=torch.uint8, device="cuda")
+        with hx.Server(p, hbm_budget=budget, streams=streams,
+                       max_batch=max_batch, arena=arena) as srv:
             # Warm-up: every batch context captures its graph once.
-            warm = [srv.submit(views[i]) for i in range(64)]
+            warm = [srv.submit(views[i]) for i in range(min(64, n))]
             for t, i in zip(warm, range(64)):
                 while srv.poll(t, views[i].shape) is None:
                     time.sleep(1e-4)
             st0 = srv.stats()
-            print(f"serve: {n} requests at {args.rate:g}/s, budget {args.budget_mb} MiB",
-                  file=sys.stderr, flush=True)
+            if verbose:
+                print(f"serve: {n} requests at {rate:g}/s, budget {budget_mb} MiB",
+                      file=sys.stderr, flush=True)
             lat = np.zeros(n)
             svc = np.zeros(n)
             outs = {}
@@ -478,8 +524,9 @@ def run_serve(args, hx):
                         del pending[t]
                         done += 1
                 if now - t0 > next_report:
-                    print(f"serve: {now - t0:.1f} s, {done} done, {len(pending)} pending",
-                          file=sys.stderr, flush=True)
+                    if verbose:
+                        print(f"serve: {now - t0:.1f} s, {done} done, {len(pending)} pending",
+                              file=sys.stderr, flush=True)
                     next_report += 1.0
                 if done != last_done:
                     last_done, last_change = done, now
@@ -490,35 +537,55 @@ def run_serve(args, hx):
                     time.sleep(max(0.0, min(2e-4, t0 + arrivals[i] - srv.now())))
             t_end = srv.now()
             st = srv.stats()
-        # Served masks against the per-image call (bit-exact), on a sample.
-        same = True
+        del arena
+    # Served masks against the per-image call (bit-exact), on a sample.
+    same = True
+    with hx.Pipeline(ksize=5, sigma=1.0, theta=0.1, max_pixels=1 << 24) as q:
         for k, m in outs.items():
-            ref = p.edge_detect(torch.from_numpy(np.ascontiguousarray(views[k])).cuda())
+            ref = q.edge_detect(torch.from_numpy(np.ascontiguousarray(views[k])).cuda())
             same &= bool(np.array_equal(ref.cpu().numpy(), m))
     span = t_end - t0
+    return {
+        "workload": f"serve-{n}-poisson-{rate:g}-64..4096-k5",
+        "mpx_s": round(total_px / span / 1e6, 1),
+        "latency_ms": percentiles(lat),
+        "latency_ms_mean": round(float(lat.mean()) * 1e3, 3),
+        "service_ms": percentiles(svc),
+        "offered_mpx_s": round(total_px / arrivals[-1] / 1e6, 1),
+        "requests": n, "rate_per_s": rate, "pixels": total_px, "budget_mib": budget_mb,
+        "streams": streams, "max_batch": max_batch, "pool_images": pool_n,
+        "span_s": round(span, 3),
+        "batches": st["batches"] - st0["batches"],
+        "mean_batch": round(n / max(1, st["batches"] - st0["batches"]), 2),
+        "peak_arena_mib": round(st["peak_bytes"] / 2**20, 1),
+        "pipeline_scratch_mib": round(own / 2**20, 1),
+        "sample_masks_identical_to_per_image": same,
+        "sample": len(outs),
+    }
+
+
+def run_serve(args, hx):
+    """The serving workload alone: its line carries throughput and the
+    latency percentiles."""
+    r = serve_leg(hx, args.requests, args.rate, args.budget_mb, args.streams,
+                  args.max_batch)
     line = {
         "metric": METRIC,
-        "value": round(total_px / span / 1e6, 1),
+        "value": r["mpx_s"],
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"serve-{n}-poisson-{args.rate:g}-64..4096-k5",
-                   "requests": n, "rate_per_s": args.rate, "pixels": total_px,
-                   "budget_mib": args.budget_mb, "streams": args.streams,
-                   "max_batch": args.max_batch},
-        "latency_ms": percentiles(lat),
-        "latency_ms_mean": round(float(lat.mean()) * 1e3, 3),
-        "service_ms": percentiles(svc),
-        "offered_mpx_s": round(total_px / arrivals[-1] / 1e6, 1),
-        "span_s": round(span, 3),
-        "batches": st["batches"] - st0["batches"],
-        "mean_batch": round(n / max(1, st["batches"] - st0["batches"]), 2),
-        "peak_arena_mib": round(st["peak_bytes"] / 2**20, 1),
-        "sample_masks_identical_to_per_image": same,
-        "sample": len(outs),
+        "config": {"workload": r["workload"], "requests": r["requests"],
+                   "rate_per_s": r["rate_per_s"], "pixels": r["pixels"],
+                   "budget_mib": r["budget_mib"], "streams": r["streams"],
+                   "max_batch": r["max_batch"]},
     }
+    line.update({k: v for k, v in r.items() if k not in ("workload", "mpx_s", "requests",
+                                                          "rate_per_s", "pixels",
+                                                          "budget_mib", "streams",
+                                                          "max_batch")})
     print(json.dumps(line), flush=True)
 
 

@@ -74,8 +74,8 @@ typedef struct hx_server hx_server;
  *              pixel it leaves at 0 is 0 under the true max too) and lists
  *              the pixels it set, with their G^2; pass 2 re-decides only
  *              those against the true max.  Exact for every input; fast
- *              when the listed pixels are few.  Runs the 256 x 64 sweep
- *              tile only. */
+ *              when the listed pixels are few.  Runs 256-column sweep
+ *              tiles of 32..256 rows (a multiple of 8). */
 enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2,
        HX_PASS_SPECULATE = 3 };
 
@@ -107,11 +107,33 @@ typedef struct {
     int32_t tile_w, tile_h, fusion_depth, pass_mode, reduce_mode;
 } hx_schedule;
 
+/* Which call forms a pipeline holds scratch for (hx_params.forms; 0 means
+ * all of them).  Each form's scratch is allocated once, at creation, sized
+ * by max_pixels and max_images; a call of a form the pipeline was created
+ * without returns HX_E_UNSUPPORTED and enqueues nothing.
+ *  IMAGE:        per-image calls at fusion depth 4 (STORE / RECOMPUTE):
+ *                one max slot and a pass-1 code plane (4 B per pixel).
+ *  STAGES:       fusion depths 1-3, the stage hook, the reduction variants:
+ *                B, L, G^2 and Z planes (13 B per pixel) and the tree's
+ *                partial maxima.
+ *  BATCH:        batched calls (and per-image SPECULATE): per batch context
+ *                the max slots, bounds, descriptor table and its pinned
+ *                staging copy, and the listed-pixel store of SPECULATE
+ *                (1.25 B per pixel).
+ *  BATCH_STORE:  batched calls with the STORE pass structure: per batch
+ *                context a pass-1 code plane (4 B per pixel).
+ *  SRAD:         hx_srad: its second plane, c plane and partial sums
+ *                (shared with the STAGES planes when both are present). */
+enum { HX_FORM_IMAGE = 1, HX_FORM_STAGES = 2, HX_FORM_BATCH = 4,
+       HX_FORM_BATCH_STORE = 8, HX_FORM_SRAD = 16, HX_FORM_ALL = 31 };
+
 /* Pipeline parameters: the constants of the computation plus the "dynamic
  * constants" (Collections and Dynamic Constants) that size every scratch
- * buffer once, at creation.  Zero fields take defaults: ksize 5,
- * sigma 1.0, thresh_frac 0.1, schedule from the autotuner cache or the
- * built-in default, max_pixels 2^25, max_images 1024. */
+ * buffer once, at creation (Global Code Motion: allocation is hoisted out
+ * of every call).  Zero fields take defaults: ksize 5, sigma 1.0,
+ * thresh_frac 0.1, schedule from the autotuner cache or the built-in
+ * default, max_pixels 2^25, max_images 1024, forms HX_FORM_ALL,
+ * batch_contexts 4. */
 typedef struct {
     int32_t ksize;            /* odd, 1..15; fused kernels need 3, 5 or 7 */
     float sigma;              /* > 0                                       */
@@ -119,6 +141,8 @@ typedef struct {
     int32_t tile_w, tile_h, fusion_depth, pass_mode;  /* 0 = automatic    */
     int64_t max_pixels;       /* max sum of H*W over one call            */
     int64_t max_images;       /* max images in one batched call          */
+    int32_t forms;            /* HX_FORM_* bits; 0 = HX_FORM_ALL          */
+    int32_t batch_contexts;   /* batched calls in flight at once, 1..8    */
 } hx_params;
 
 /* One image: device pointers.  src is H rows of `width` fp32 values with a
@@ -131,17 +155,25 @@ typedef struct {
     int64_t mask_pitch;
 } hx_image;
 
-/* Create a pipeline on `device`.  Allocates all fixed scratch (per-image
- * max slots, counters, the batch descriptor table and its pinned staging
- * copy).  Buffers whose size depends on the images (the pass-1 store
- * buffer, the stage buffers of fusion depths 1..3, the descriptor table)
- * are allocated by the first call that needs them and grow when a later
- * call needs more; warm a pipeline up before capturing its calls in a
- * graph.
+/* Create a pipeline on `device`.  Allocates ALL of its scratch, for the
+ * forms in params->forms, sized by max_pixels and max_images (the sizes
+ * per form are listed with HX_FORM_*; hx_pipeline_memory reports the
+ * totals).  No later call on the pipeline allocates or frees device or
+ * pinned host memory.  Per-image planes hold H * round_up(W, 4) <=
+ * max_pixels + 3 * 65536 elements, so an image taller than 65536 rows and
+ * narrower than 4 columns may not fit them (HX_E_UNSUPPORTED).
  * Returns HX_E_INVALID for bad parameters, HX_E_NOMEM / HX_E_HIP on
  * allocation or device errors.  *out is set only on HX_OK. */
 hx_status hx_pipeline_create(const hx_params* params, int device,
                              hx_pipeline** out);
+
+/* The pipeline's own memory: device bytes and pinned host bytes it holds
+ * (all allocated by hx_pipeline_create), and the number of allocation
+ * calls (device or pinned) it has made since creation -- constant after
+ * hx_pipeline_create returns, which tests use to check that no call path
+ * allocates.  Any pointer may be NULL. */
+hx_status hx_pipeline_memory(const hx_pipeline* p, size_t* device_bytes,
+                             size_t* pinned_bytes, uint64_t* allocations);
 
 /* Wait for the pipeline's outstanding work, release its memory.  NULL is a
  * no-op. */
@@ -201,21 +233,30 @@ hx_status hx_pipeline_get_schedule(const hx_pipeline* p, int64_t height,
                                    int64_t width, hx_schedule* out);
 
 /* One image, the per-image form: a handful of kernel launches on `stream`.
- * d_max (device, nullable) receives M = max G as one float. */
+ * d_max (device, nullable) receives M = max G as one float.  Per-image
+ * calls share one set of the pipeline's scratch: a call on a different
+ * stream from the previous per-image call (hx_edge_detect,
+ * hx_edge_detect_stages, hx_srad) first makes its stream wait for that
+ * call's work, so calls on several streams are correct but do not
+ * overlap.  (SPECULATE per-image calls use the batch contexts instead.) */
 hx_status hx_edge_detect(hx_pipeline* p, const hx_image* img, float* d_max,
                          hipStream_t stream);
 
-/* n images of any sizes in ONE graph launch (captured once, replayed for
- * every call): a reset of the per-image max slots, then one persistent
- * kernel over the flattened list of (image, tile) pass-1 items, then one
- * over the (image, row-run or tile) pass-2 items.  No workgroup waits on
- * another; the kernel boundary makes each image's max final before its
- * mask is written.  imgs is a HOST array of n descriptors (device pointers
+/* n images of any sizes in one launch sequence: [a reset of the per-image
+ * max slots | SPECULATE's pass 0], then one kernel over the flattened list
+ * of (image, tile) pass-1 items, then one over the pass-2 items.  No
+ * workgroup waits on another; the kernel boundary makes each image's max
+ * final before its mask is written.  A batch that a batch context already
+ * ran (same descriptors, outputs and pass structure) replays its captured
+ * HIP graph.  imgs is a HOST array of n descriptors (device pointers
  * inside); it is copied before the call returns.  d_max (device,
  * nullable) receives n floats.  Requires 1 <= n <= max_images and
  * sum H*W <= max_pixels.  Each image's result is bit-identical to
- * hx_edge_detect on it alone.  Batched calls on different streams use
- * separate scratch (up to six in flight per pipeline). */
+ * hx_edge_detect on it alone.  Batched calls use one of batch_contexts
+ * scratch sets each, so calls on different streams overlap; a call whose
+ * context is still in use waits (on the host) for it.  A batch with more
+ * tiles than a context's descriptor table holds (only possible with many
+ * images a few pixels wide or tall) runs as several launches in turn. */
 hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs,
                                  int32_t n, float* d_max, hipStream_t stream);
 
@@ -237,8 +278,22 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img,
 hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
                       const char* cache_path);
 
-/* Load schedules from a cache written by hx_autotune (entries for other
- * ksize values or devices are ignored). */
+/* The batch autotuner: times the batched call on the caller's batch (imgs,
+ * n: as hx_edge_detect_batched; their masks are written, with the same
+ * bits as any schedule gives) under every candidate -- sweep tile heights
+ * 32..160 rows x pass structures SPECULATE, RECOMPUTE and, when the
+ * pipeline holds HX_FORM_BATCH_STORE, STORE; median of five graph replays
+ * each -- and keeps the fastest for the batch's class (floor(log2) of its
+ * total pixels and of n): later batched calls of that class use it unless
+ * the pass structure is fixed or a schedule forced.  Blocking.  Appends one
+ * {"batch_trial": ...} line per candidate and the chosen {"batch": ...}
+ * line to cache_path (NULL = do not persist); *tile_h and *pass_mode
+ * (nullable) receive the choice. */
+hx_status hx_autotune_batch(hx_pipeline* p, const hx_image* imgs, int32_t n,
+                            const char* cache_path, int32_t* tile_h, int32_t* pass_mode);
+
+/* Load schedules from a cache written by hx_autotune or hx_autotune_batch
+ * (entries for other ksize values are ignored). */
 hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path);
 
 /* --------------------------------------------------------------- SRAD --
@@ -277,10 +332,13 @@ typedef struct {
 } hx_serve_params;
 
 /* d_arena/arena_bytes: one caller-owned device allocation (e.g. a torch
- * uint8 tensor) that the server sub-allocates request buffers from; the
- * effective budget is min(hbm_budget, arena_bytes).  The server owns a
- * scheduler thread and its streams; the pipeline must outlive it and must
- * not be used by anyone else meanwhile. */
+ * uint8 tensor) that the server sub-allocates request buffers from.  The
+ * pipeline's own scratch (hx_pipeline_memory) counts against the budget:
+ * request buffers may occupy at most min(hbm_budget - pipeline device
+ * bytes, arena_bytes); HX_E_INVALID if the budget does not exceed the
+ * pipeline's scratch, HX_E_UNSUPPORTED if the pipeline lacks
+ * HX_FORM_BATCH.  The server owns a scheduler thread and its streams; the
+ * pipeline must outlive it and must not be used by anyone else meanwhile. */
 hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp,
                           void* d_arena, size_t arena_bytes, hx_server** out);
 

@@ -47,16 +47,18 @@ hx_status hip_fail(hipError_t e, const char* what) {
                 hipGetErrorString(e));
 }
 
-hipError_t DevBuf::ensure(size_t need) {
-    if (need <= bytes && ptr) return hipSuccess;
+hipError_t DevBuf::alloc(size_t n, MemStats& m) {
     release();
-    const size_t n = need < 256 ? 256 : need;
-    hipError_t e = hipMalloc(&ptr, n);
+    if (n == 0) return hipSuccess;
+    const size_t want = n < 256 ? 256 : n;
+    ++m.allocations;
+    hipError_t e = hipMalloc(&ptr, want);
     if (e != hipSuccess) {
         ptr = nullptr;
         return e;
     }
-    bytes = n;
+    bytes = want;
+    m.device_bytes += want;
     return hipSuccess;
 }
 
@@ -64,6 +66,49 @@ void DevBuf::release() {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+}
+
+hipError_t HostBuf::alloc(size_t n, MemStats& m) {
+    release();
+    if (n == 0) return hipSuccess;
+    ++m.allocations;
+    hipError_t e = hipHostMalloc(&ptr, n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    bytes = n;
+    m.pinned_bytes += n;
+    return hipSuccess;
+}
+
+void HostBuf::release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+// Elements of one per-image plane (rows of round_up(W, 4) elements).
+static int64_t plane_capacity(int64_t max_pixels) { return max_pixels + 3 * 65536; }
+
+static int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
+
+static int64_t plane_need(int64_t H, int64_t W) { return H * round4(W); }
+
+// Capacities of one batch context.  Pass-1 items: about twice the tiles
+// of max_pixels in full tiles plus 16 per image; a batch of images so thin
+// or small that it needs more runs as several launches (run_batched).
+static BatchCaps batch_caps(const hx_params& prm, bool store_plane) {
+    BatchCaps c;
+    const SweepGeom g{prm.ksize, batch_sweep_c(), kBatchTyMin};
+    const int64_t P = prm.max_pixels, n = prm.max_images;
+    c.items1 = 2 * ((P + (int64_t)g.ow() * g.ty - 1) / ((int64_t)g.ow() * g.ty)) + 16 * n + 4096;
+    c.items2 = std::max<int64_t>(c.items1, P / 1024 + 2 * n + 1024);
+    c.items0 = 5 * c.items1;
+    c.list_entries = P / 16 + 16;
+    c.table_bytes = batch_table_bytes((int)n, c.items1, c.items2, c.items0);
+    c.code_elems = store_plane ? plane_capacity(P) : 0;
+    return c;
 }
 
 ShapeClass shape_class(int64_t H, int64_t W) {
@@ -74,8 +119,6 @@ ShapeClass shape_class(int64_t H, int64_t W) {
     };
     return ShapeClass{lg(H), lg(W)};
 }
-
-static int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
 
 static bool fused_ks(int ks) { return ks == 3 || ks == 5 || ks == 7; }
 
@@ -104,9 +147,9 @@ hx_status validate_schedule(const hx_pipeline* p, const hx_schedule& s) {
         s.pass_mode != HX_PASS_RECOMPUTE && s.pass_mode != HX_PASS_SPECULATE)
         return fail(HX_E_INVALID, "pass_mode %d unknown", s.pass_mode);
     if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE &&
-        (s.tile_w != 64 * batch_sweep_c() || s.tile_h != batch_sweep_ty()))
-        return fail(HX_E_INVALID, "SPECULATE runs the %dx%d sweep tile only",
-                    64 * batch_sweep_c(), batch_sweep_ty());
+        (s.tile_w != 64 * batch_sweep_c() || s.tile_h < kBatchTyMin || s.tile_h > kBatchTyMax))
+        return fail(HX_E_INVALID, "SPECULATE runs %d-column sweep tiles of %d..%d rows",
+                    64 * batch_sweep_c(), kBatchTyMin, kBatchTyMax);
     return HX_OK;
 }
 
@@ -137,7 +180,8 @@ hx_schedule choose_schedule(const hx_pipeline* p, int64_t H, int64_t W) {
     // SPECULATE runs the batch sweep's tile; a tuned tile of another shape
     // gives way to it unless the tile was fixed at creation.
     if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE && !p->prm.tile_w &&
-        !p->prm.tile_h) {
+        !p->prm.tile_h &&
+        (s.tile_w != 64 * batch_sweep_c() || s.tile_h < kBatchTyMin || s.tile_h > kBatchTyMax)) {
         s.tile_w = 64 * batch_sweep_c();
         s.tile_h = batch_sweep_ty();
     }
@@ -182,21 +226,33 @@ static ImgArgs base_args(const hx_image* img, uint32_t* slot, float* d_max) {
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
+// Does the pipeline hold scratch for `form`?
+static bool has_form(const hx_pipeline* p, int form) { return (p->prm.forms & form) != 0; }
+
 hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
                     const hx_schedule& s, hipStream_t stream) {
     // SPECULATE runs the batch kernels on a batch of one.
     if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE)
-        return run_batched(p, img, 1, d_max, HX_PASS_SPECULATE, stream);
-    ImgArgs a = base_args(img, p->slot1, d_max);
-    const size_t plane = (size_t)a.H * (size_t)a.op;
+        return run_batched(p, img, 1, d_max, HX_PASS_SPECULATE, s.tile_h, stream);
+    const int need_form = s.fusion_depth == 4 ? HX_FORM_IMAGE : HX_FORM_STAGES;
+    if (!has_form(p, need_form))
+        return fail(HX_E_UNSUPPORTED, "the pipeline was created without the %s scratch",
+                    need_form == HX_FORM_IMAGE ? "HX_FORM_IMAGE" : "HX_FORM_STAGES");
+    if (plane_need(img->height, img->width) > p->plane_elems)
+        return fail(HX_E_UNSUPPORTED,
+                    "a %lldx%lld image needs stage planes of %lld elements; the pipeline's "
+                    "hold %lld (raise max_pixels)",
+                    (long long)img->height, (long long)img->width,
+                    (long long)plane_need(img->height, img->width), (long long)p->plane_elems);
+    uint32_t* slot = (uint32_t*)p->slot1.ptr;
+    ImgArgs a = base_args(img, slot, d_max);
     const float theta = p->prm.thresh_frac;
     const int ks = p->prm.ksize;
-    HX_TRY(launch_fill_u32(p->slot1, 0u, 1, stream));
+    HX_TRY(launch_fill_u32(slot, 0u, 1, stream));
     if (s.fusion_depth == 4) {
         const int c = s.tile_w / 64;
         if (s.pass_mode == HX_PASS_STORE) {
-            HX_TRY(p->code1.ensure(plane * sizeof(float)));
-            a.fout = (float*)p->code1.ptr;
+            a.fout = (float*)p->planeA.ptr;
             HX_TRY(launch_sweep(SM_STORE, ks, c, s.tile_h, a, p->taps, theta, stream));
             HX_TRY(launch_threshold_code(a, theta, stream));
         } else {
@@ -208,23 +264,20 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
     }
     StageBufs b{};
     b.op = a.op;
-    HX_TRY(p->bufG2.ensure(plane * sizeof(float)));
-    HX_TRY(p->bufZ.ensure(plane));
-    b.G2 = (float*)p->bufG2.ptr;
-    b.Z = (uint8_t*)p->bufZ.ptr;
+    b.B = (float*)p->planeA.ptr;
+    b.L = (float*)p->planeL.ptr;
+    b.G2 = (float*)p->planeG2.ptr;
+    b.Z = (uint8_t*)p->planeZ.ptr;
+    b.partial = (float*)p->bufPart.ptr;
     const int tw1 = 64, th1 = 16;  // per-pixel second kernels of depths 2, 3
     if (s.fusion_depth == 2 || s.fusion_depth == 3) {
         const int c = s.tile_w / 64;
-        DevBuf& first = s.fusion_depth == 2 ? p->bufB : p->bufL;
-        HX_TRY(first.ensure(plane * sizeof(float)));
-        a.fout = (float*)first.ptr;
+        a.fout = s.fusion_depth == 2 ? b.B : b.L;
         a.g2 = b.G2;
         if (s.fusion_depth == 2) {
-            b.B = a.fout;
             HX_TRY(launch_sweep(SM_BG, ks, c, s.tile_h, a, p->taps, theta, stream));
             HX_TRY(launch_lap_zero_cross(a, b, tw1, th1, stream));
         } else {
-            b.L = a.fout;
             HX_TRY(launch_sweep(SM_BGL, ks, c, s.tile_h, a, p->taps, theta, stream));
             HX_TRY(launch_zero_cross(a, b, b.L, tw1, th1, stream));
         }
@@ -232,14 +285,6 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
         return HX_OK;
     }
     // Depth 1: one kernel per stage.
-    HX_TRY(p->bufB.ensure(plane * sizeof(float)));
-    HX_TRY(p->bufL.ensure(plane * sizeof(float)));
-    b.B = (float*)p->bufB.ptr;
-    b.L = (float*)p->bufL.ptr;
-    if (s.reduce_mode == HX_REDUCE_TWO_LEVEL) {
-        HX_TRY(p->bufPart.ensure((size_t)kTreeThreads * sizeof(float)));
-        b.partial = (float*)p->bufPart.ptr;
-    }
     HX_TRY(launch_blur(a, b, p->taps, ks, s.tile_w, s.tile_h, stream));
     HX_TRY(launch_laplacian(a, b, s.tile_w, s.tile_h, stream));
     HX_TRY(launch_zero_cross(a, b, b.L, s.tile_w, s.tile_h, stream));
@@ -248,10 +293,51 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
     return HX_OK;
 }
 
+// Per-image calls share the pipeline's per-image scratch: one on a stream
+// other than the previous one's waits (on the device) for the previous
+// one's work first.
+static hx_status img_order_begin(hx_pipeline* p, hipStream_t stream) {
+    if (p->img_used && p->img_stream != stream)
+        HX_TRY(hipStreamWaitEvent(stream, p->img_ev, 0));
+    return HX_OK;
+}
+static hx_status img_order_end(hx_pipeline* p, hipStream_t stream) {
+    HX_TRY(hipEventRecord(p->img_ev, stream));
+    p->img_used = true;
+    p->img_stream = stream;
+    return HX_OK;
+}
+
+hx_status run_image_ordered(hx_pipeline* p, const hx_image* img, float* d_max,
+                            const hx_schedule& s, hipStream_t stream) {
+    if (s.fusion_depth == 4 && s.pass_mode == HX_PASS_SPECULATE)
+        return run_image(p, img, d_max, s, stream);
+    hx_status st = img_order_begin(p, stream);
+    if (st != HX_OK) return st;
+    st = run_image(p, img, d_max, s, stream);
+    hx_status st2 = img_order_end(p, stream);
+    return st != HX_OK ? st : st2;
+}
+
 // ------------------------------------------------------------- batched --
+// Allocate one batch context: everything a batched call on it can need,
+// sized by the pipeline's capacities.
 static hx_status ctx_init(hx_pipeline* p, BatchContext& c) {
     if (c.ready) return HX_OK;
-    HX_TRY(hipMalloc(&c.slots, sizeof(uint32_t) * p->prm.max_images));
+    MemStats& m = p->mem;
+    const BatchCaps& k = p->caps;
+    const int64_t n = p->prm.max_images;
+    HX_TRY(c.slots.alloc(sizeof(uint32_t) * n, m));
+    // Bounds (8 B each) and the epoch, cleared once here.
+    const int64_t words = 2 * n + 2;
+    HX_TRY(c.spec_state.alloc(sizeof(uint32_t) * words, m));
+    HX_TRY(hipMemset(c.spec_state.ptr, 0, sizeof(uint32_t) * words));
+    HX_TRY(c.table.alloc(k.table_bytes, m));
+    HX_TRY(c.h_table.alloc(k.table_bytes, m));
+    HX_TRY(c.cand_code.alloc((size_t)k.list_entries * batch_sweep_c() * sizeof(float), m));
+    HX_TRY(c.cand_row.alloc((size_t)k.list_entries * sizeof(int32_t), m));
+    HX_TRY(c.cand_n.alloc((size_t)k.items1 * sizeof(uint32_t), m));
+    if (k.code_elems) HX_TRY(c.code.alloc((size_t)k.code_elems * sizeof(float), m));
     HX_TRY(hipEventCreateWithFlags(&c.ev_done, hipEventDisableTiming));
     for (auto& e : c.ev_t) HX_TRY(hipEventCreate(&e));
     c.ready = true;
@@ -264,13 +350,13 @@ static void ctx_release(BatchContext& c) {
         if (c.graph[i]) (void)hipGraphDestroy(c.graph[i]);
     }
     c.table.release();
+    c.h_table.release();
+    c.slots.release();
+    c.spec_state.release();
     c.code.release();
     c.cand_code.release();
     c.cand_row.release();
     c.cand_n.release();
-    if (c.h_table) (void)hipHostFree(c.h_table);
-    if (c.slots) (void)hipFree(c.slots);
-    if (c.spec_state) (void)hipFree(c.spec_state);
     if (c.ev_done) (void)hipEventDestroy(c.ev_done);
     for (auto& e : c.ev_t)
         if (e) (void)hipEventDestroy(e);
@@ -299,7 +385,7 @@ static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipS
     const int ks = p->prm.ksize;
     hipError_t e = timed ? hipEventRecord(c.ev_t[0], s) : hipSuccess;
     if (e == hipSuccess && pass != HX_PASS_SPECULATE)
-        e = launch_batch_reset(c.table.ptr, c.slots, (int)p->prm.max_images, s);
+        e = launch_batch_reset(c.table.ptr, (uint32_t*)c.slots.ptr, (int)p->prm.max_images, s);
     if (e == hipSuccess && timed) e = hipEventRecord(c.ev_t[1], s);
     if (e == hipSuccess && pass == HX_PASS_SPECULATE)
         e = launch_batch_phase(ks, pass, 0, c.table.ptr, p->taps, phase_grid(c, 0), s);
@@ -313,11 +399,9 @@ static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipS
     return e;
 }
 
-// Capture the launches once per (context, pass mode, table address, item
-// counts).
+// Capture the launches once per (context, pass mode, item counts).
 static hx_status ctx_graph(hx_pipeline* p, BatchContext& c, int pass) {
-    if (c.exec[pass] && c.graph_table[pass] == c.table.ptr &&
-        std::memcmp(c.graph_items[pass], c.n_items, sizeof c.n_items) == 0)
+    if (c.exec[pass] && std::memcmp(c.graph_items[pass], c.n_items, sizeof c.n_items) == 0)
         return HX_OK;
     if (c.exec[pass]) {
         (void)hipGraphExecDestroy(c.exec[pass]);
@@ -343,34 +427,124 @@ static hx_status ctx_graph(hx_pipeline* p, BatchContext& c, int pass) {
     }
     c.graph[pass] = g;
     c.exec[pass] = ex;
-    c.graph_table[pass] = c.table.ptr;
     std::memcpy(c.graph_items[pass], c.n_items, sizeof c.n_items);
     return HX_OK;
 }
 
+// Work items of one image in each pass, and its STORE code elements.
+struct ImgWork {
+    int64_t tiles = 0, p2 = 0, p0 = 0, code = 0;
+};
+static ImgWork img_work(const hx_image& im, int pass, const SweepGeom& geo) {
+    ImgWork w;
+    w.tiles = geo.tiles(im.height, im.width);
+    const int64_t rb = batch_p2_rows(im.width);
+    w.p2 = pass == HX_PASS_STORE ? (im.height + rb - 1) / rb : w.tiles;
+    w.p0 = pass == HX_PASS_SPECULATE ? batch_sample_items(geo.ks, im.height, im.width) : 0;
+    w.code = pass == HX_PASS_STORE ? plane_need(im.height, im.width) : 0;
+    return w;
+}
+static bool fits(const BatchCaps& k, const ImgWork& t, int pass) {
+    return t.tiles <= k.items1 && t.p2 <= k.items2 && t.p0 <= k.items0 &&
+           (pass != HX_PASS_STORE || t.code <= k.code_elems);
+}
+
+// Build the descriptor table of a batch in the context's pinned staging
+// buffer and copy it to the device on `stream`.  The caller has checked
+// that the batch fits the context's capacities.
 static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* imgs,
                              int32_t n, float* d_max, int pass, const SweepGeom& geo,
-                             hipStream_t stream);
+                             hipStream_t stream) {
+    c.last_pass = -1;  // the device table is stale until the copy is queued
+    const bool spec = pass == HX_PASS_SPECULATE;
+    std::vector<ImgWork> w(n);
+    ImgWork tot;
+    for (int i = 0; i < n; ++i) {
+        w[i] = img_work(imgs[i], pass, geo);
+        tot.tiles += w[i].tiles;
+        tot.p2 += w[i].p2;
+        tot.p0 += w[i].p0;
+        tot.code += w[i].code;
+    }
+    if (!fits(p->caps, tot, pass))
+        return fail(HX_E_INVALID, "batch exceeds the context's capacities");
+    const size_t bytes = batch_table_bytes(n, tot.tiles, tot.p2, tot.p0);
 
-hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
-                      float* d_max, int pass, hipStream_t stream) {
-    const int ks = p->prm.ksize;
-    const SweepGeom geo{ks, batch_sweep_c(), batch_sweep_ty()};
-    std::lock_guard<std::mutex> lk(p->batch_mu);
-    if (pass < HX_PASS_STORE || pass > HX_PASS_SPECULATE)
-        return fail(HX_E_INVALID, "pass_mode %d unknown", pass);
-    BatchContext& c = p->ctx[p->next_ctx];
-    p->next_ctx = (p->next_ctx + 1) % hx_pipeline::kContexts;
-    hx_status st = ctx_init(p, c);
-    if (st != HX_OK) return st;
-    st = ctx_wait(c);
-    if (st != HX_OK) return st;
+    // Fill the pinned table: header, images, pass-1, pass-2, pass-0 items.
+    uint8_t* h = (uint8_t*)c.h_table.ptr;
+    BatchHeader hdr{};
+    hdr.n_images = n;
+    hdr.n_items1 = (int32_t)tot.tiles;
+    hdr.n_items2 = (int32_t)tot.p2;
+    hdr.pass_mode = pass;
+    hdr.theta = p->prm.thresh_frac;
+    hdr.n_items0 = (int32_t)tot.p0;
+    if (spec) {
+        hdr.cand_code = (float*)c.cand_code.ptr;
+        hdr.cand_row = (int32_t*)c.cand_row.ptr;
+        hdr.cand_n = (uint32_t*)c.cand_n.ptr;
+        hdr.bound = (unsigned long long*)c.spec_state.ptr;
+        hdr.epoch = (uint32_t*)(hdr.bound + p->prm.max_images);
+    }
+    std::memcpy(h, &hdr, sizeof hdr);
+    ImgArgs* ia = (ImgArgs*)(h + sizeof(BatchHeader));
+    int64_t code_off = 0, list_off = 0;
+    for (int i = 0; i < n; ++i) {
+        ia[i] = base_args(&imgs[i], (uint32_t*)c.slots.ptr + i, d_max ? d_max + i : nullptr);
+        ia[i].ty = geo.ty;
+        if (pass == HX_PASS_STORE) ia[i].fout = (float*)c.code.ptr + code_off;
+        code_off += w[i].code;
+        if (spec) {
+            const uint32_t cap = spec_tile_cap(imgs[i].height, imgs[i].width, w[i].tiles);
+            ia[i].list_base = (uint32_t)list_off;
+            ia[i].list_cap = cap;
+            list_off += (int64_t)cap * w[i].tiles;
+        }
+    }
+    if (list_off > p->caps.list_entries)
+        return fail(HX_E_INVALID, "listing capacity exceeded");  // cannot happen: sum <= P/16
+    BatchItem* it = (BatchItem*)(ia + n);
+    for (int i = 0; i < n; ++i)
+        for (int64_t t = 0; t < w[i].tiles; ++t) *it++ = BatchItem{i, (int32_t)t};
+    for (int i = 0; i < n; ++i)
+        for (int64_t t = 0; t < w[i].p2; ++t) *it++ = BatchItem{i, (int32_t)t};
+    for (int i = 0; i < n; ++i)
+        for (int64_t t = 0; t < w[i].p0; ++t) *it++ = BatchItem{i, (int32_t)t};
 
-    const bool same = c.last_pass == pass && c.last_dmax == d_max &&
-                      c.last_imgs.size() == (size_t)n &&
+    HX_TRY(hipMemcpyAsync(c.table.ptr, h, bytes, hipMemcpyHostToDevice, stream));
+    c.n_items[0] = tot.p0;
+    c.n_items[1] = tot.tiles;
+    c.n_items[2] = tot.p2;
+    c.last_imgs.assign(imgs, imgs + n);
+    c.last_dmax = d_max;
+    c.last_pass = pass;
+    c.last_ty = geo.ty;
+    return HX_OK;
+}
+
+// One image whose tiles alone exceed a context's table: the per-image
+// RECOMPUTE form (two sweeps and no tables), with the image's max in the
+// context's first slot.  Same bits as the batched passes.
+static hx_status run_oversized(hx_pipeline* p, BatchContext& c, const hx_image& im,
+                               float* d_max, hipStream_t stream) {
+    ImgArgs a = base_args(&im, (uint32_t*)c.slots.ptr, d_max);
+    const int ks = p->prm.ksize, cw = batch_sweep_c(), ty = batch_sweep_ty();
+    HX_TRY(launch_fill_u32(a.slot, 0u, 1, stream));
+    HX_TRY(launch_sweep(SM_MAXONLY, ks, cw, ty, a, p->taps, p->prm.thresh_frac, stream));
+    HX_TRY(launch_sweep(SM_MASK, ks, cw, ty, a, p->taps, p->prm.thresh_frac, stream));
+    if (d_max) HX_TRY(launch_write_max(a, stream));
+    return HX_OK;
+}
+
+// Launch a batch that fits one context on context c.
+static hx_status launch_on(hx_pipeline* p, BatchContext& c, const hx_image* imgs, int32_t n,
+                           float* d_max, int pass, const SweepGeom& geo, bool allow_graph,
+                           hipStream_t stream) {
+    const bool same = c.ready && c.last_pass == pass && c.last_ty == geo.ty &&
+                      c.last_dmax == d_max && c.last_imgs.size() == (size_t)n &&
                       std::memcmp(c.last_imgs.data(), imgs, sizeof(hx_image) * n) == 0;
     if (!same) {
-        st = build_table(p, c, imgs, n, d_max, pass, geo, stream);
+        hx_status st = build_table(p, c, imgs, n, d_max, pass, geo, stream);
         if (st != HX_OK) return st;
     }
     // A batch seen again on this context replays a captured graph; a new
@@ -380,101 +554,135 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
     if (p->timing) {
         HX_TRY(enqueue_phases(p, c, pass, stream, true));
         p->last_timed_ctx = (int)(&c - p->ctx);
-    } else if (no_graph || !same) {
+    } else if (no_graph || !same || !allow_graph) {
         HX_TRY(enqueue_phases(p, c, pass, stream));
     } else {
-        st = ctx_graph(p, c, pass);
+        hx_status st = ctx_graph(p, c, pass);
         if (st != HX_OK) return st;
         HX_TRY(hipGraphLaunch(c.exec[pass], stream));
     }
-    HX_TRY(hipEventRecord(c.ev_done, stream));
-    c.in_flight = true;
     return HX_OK;
 }
 
-// Build the descriptor table of a batch in the context's pinned staging
-// buffer and copy it to the device on `stream`.
-static hx_status build_table(hx_pipeline* p, BatchContext& c, const hx_image* imgs,
-                             int32_t n, float* d_max, int pass, const SweepGeom& geo,
-                             hipStream_t stream) {
-    c.last_pass = -1;  // the device table is stale until the copy is queued
-    // Item counts and pass-1 store offsets.
-    const bool spec = pass == HX_PASS_SPECULATE;
-    std::vector<int64_t> tiles(n), p2n(n), p0n(n), off(n);
-    int64_t n1 = 0, n2 = 0, n0 = 0, code_elems = 0;
-    for (int i = 0; i < n; ++i) {
-        tiles[i] = geo.tiles(imgs[i].height, imgs[i].width);
-        const int64_t rb = batch_p2_rows(imgs[i].width);
-        p2n[i] = pass == HX_PASS_STORE ? (imgs[i].height + rb - 1) / rb : tiles[i];
-        p0n[i] = spec ? batch_sample_items(geo.ks, imgs[i].height, imgs[i].width) : 0;
-        n1 += tiles[i];
-        n2 += p2n[i];
-        n0 += p0n[i];
-        off[i] = code_elems;
-        if (pass == HX_PASS_STORE) code_elems += imgs[i].height * round4(imgs[i].width);
-    }
-    if (n1 >= (int64_t(1) << 31) || n2 >= (int64_t(1) << 31) || n0 >= (int64_t(1) << 31))
-        return fail(HX_E_INVALID, "batch has too many work items");
-    if (pass == HX_PASS_STORE) HX_TRY(c.code.ensure((size_t)code_elems * sizeof(float)));
-    if (spec && !c.spec_state) {
-        // Bounds (8 B each) and the epoch, cleared once by a fill kernel.
-        const int64_t words = 2 * p->prm.max_images + 2;
-        HX_TRY(hipMalloc(&c.spec_state, sizeof(uint32_t) * words));
-        HX_TRY(launch_fill_u32((uint32_t*)c.spec_state, 0u, words, stream));
-    }
-    if (spec) {
-        const size_t entries = (size_t)n1 * batch_spec_entries();
-        HX_TRY(c.cand_code.ensure(entries * geo.c * sizeof(float)));
-        HX_TRY(c.cand_row.ensure(entries * sizeof(int32_t)));
-        HX_TRY(c.cand_n.ensure((size_t)n1 * sizeof(uint32_t)));
-    }
-    const size_t bytes = batch_table_bytes(n, n1, n2, n0);
-    HX_TRY(c.table.ensure(bytes));
-    if (c.h_table_bytes < bytes) {
-        if (c.h_table) (void)hipHostFree(c.h_table);
-        c.h_table = nullptr;
-        c.h_table_bytes = 0;
-        HX_TRY(hipHostMalloc(&c.h_table, bytes, hipHostMallocDefault));
-        c.h_table_bytes = bytes;
-    }
+BatchKey batch_key(const hx_image* imgs, int32_t n) {
+    int64_t px = 0;
+    for (int i = 0; i < n; ++i) px += imgs[i].height * imgs[i].width;
+    auto lg = [](int64_t v) {
+        int b = 0;
+        while ((v >> (b + 1)) > 0) ++b;
+        return b;
+    };
+    return BatchKey{lg(px), lg(n)};
+}
 
-    // Fill the pinned table: header, images, pass-1 items, pass-2 items.
-    uint8_t* h = (uint8_t*)c.h_table;
-    BatchHeader hdr{};
-    hdr.n_images = n;
-    hdr.n_items1 = (int32_t)n1;
-    hdr.n_items2 = (int32_t)n2;
-    hdr.pass_mode = pass;
-    hdr.theta = p->prm.thresh_frac;
-    hdr.n_items0 = (int32_t)n0;
-    if (spec) {
-        hdr.cand_code = (float*)c.cand_code.ptr;
-        hdr.cand_row = (int32_t*)c.cand_row.ptr;
-        hdr.cand_n = (uint32_t*)c.cand_n.ptr;
-        hdr.bound = (unsigned long long*)c.spec_state;
-        hdr.epoch = (uint32_t*)(hdr.bound + p->prm.max_images);
+hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
+                      float* d_max, int pass, int ty, hipStream_t stream) {
+    const int ks = p->prm.ksize;
+    {
+        auto it = p->batch_tuned.find(batch_key(imgs, n));
+        if (it != p->batch_tuned.end()) {
+            if (!ty) ty = it->second.ty;
+            // A tuned STORE needs the STORE plane; without it the default
+            // pass structure runs.
+            if (!pass && (it->second.pass != HX_PASS_STORE || has_form(p, HX_FORM_BATCH_STORE)))
+                pass = it->second.pass;
+        }
     }
-    std::memcpy(h, &hdr, sizeof hdr);
-    ImgArgs* ia = (ImgArgs*)(h + sizeof(BatchHeader));
-    for (int i = 0; i < n; ++i) {
-        ia[i] = base_args(&imgs[i], c.slots + i, d_max ? d_max + i : nullptr);
-        if (pass == HX_PASS_STORE) ia[i].fout = (float*)c.code.ptr + off[i];
+    if (!ty) ty = batch_sweep_ty();
+    if (!pass) pass = kBatchPass;
+    if (ty < kBatchTyMin || ty > kBatchTyMax || ty % 8 != 0)
+        return fail(HX_E_INVALID, "batch tile height %d not a multiple of 8 in %d..%d", ty,
+                    kBatchTyMin, kBatchTyMax);
+    const SweepGeom geo{ks, batch_sweep_c(), ty};
+    if (pass < HX_PASS_STORE || pass > HX_PASS_SPECULATE)
+        return fail(HX_E_INVALID, "pass_mode %d unknown", pass);
+    if (!has_form(p, HX_FORM_BATCH))
+        return fail(HX_E_UNSUPPORTED, "the pipeline was created without HX_FORM_BATCH scratch");
+    if (pass == HX_PASS_STORE && !has_form(p, HX_FORM_BATCH_STORE))
+        return fail(HX_E_UNSUPPORTED,
+                    "batched STORE needs a pipeline created with HX_FORM_BATCH_STORE");
+    std::lock_guard<std::mutex> lk(p->batch_mu);
+    // Which context: one that already holds this batch (its table and
+    // graph are reused as they are) and is idle; else the oldest of those
+    // holding it; else the oldest context.  Consecutive calls that
+    // alternate between a few output sets thus settle on contexts of their
+    // own, whatever the order of the first calls was.
+    auto holds = [&](const BatchContext& c) {
+        return c.ready && c.last_pass == pass && c.last_ty == ty && c.last_dmax == d_max &&
+               c.last_imgs.size() == (size_t)n &&
+               std::memcmp(c.last_imgs.data(), imgs, sizeof(hx_image) * n) == 0;
+    };
+    int pick = -1, oldest_match = -1, oldest = -1;
+    for (int i = 0; i < p->n_ctx; ++i) {
+        BatchContext& c = p->ctx[i];
+        if (holds(c)) {
+            if (!c.in_flight || hipEventQuery(c.ev_done) == hipSuccess) {
+                pick = i;
+                break;
+            }
+            if (oldest_match < 0 || c.last_use < p->ctx[oldest_match].last_use) oldest_match = i;
+        }
+        if (oldest < 0 || c.last_use < p->ctx[oldest].last_use) oldest = i;
     }
-    BatchItem* it = (BatchItem*)(ia + n);
-    for (int i = 0; i < n; ++i)
-        for (int64_t t = 0; t < tiles[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
-    for (int i = 0; i < n; ++i)
-        for (int64_t t = 0; t < p2n[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
-    for (int i = 0; i < n; ++i)
-        for (int64_t t = 0; t < p0n[i]; ++t) *it++ = BatchItem{i, (int32_t)t};
+    if (pick < 0) pick = oldest_match >= 0 ? oldest_match : oldest;
+    BatchContext& c = p->ctx[pick];
+    c.last_use = ++p->use_clock;
+    hx_status st = ctx_wait(c);
+    if (st != HX_OK) return st;
 
-    HX_TRY(hipMemcpyAsync(c.table.ptr, h, bytes, hipMemcpyHostToDevice, stream));
-    c.n_items[0] = n0;
-    c.n_items[1] = n1;
-    c.n_items[2] = n2;
-    c.last_imgs.assign(imgs, imgs + n);
-    c.last_dmax = d_max;
-    c.last_pass = pass;
+    // The common case: the whole batch fits the context.
+    ImgWork tot;
+    for (int i = 0; i < n; ++i) {
+        const ImgWork w = img_work(imgs[i], pass, geo);
+        tot.tiles += w.tiles;
+        tot.p2 += w.p2;
+        tot.p0 += w.p0;
+        tot.code += w.code;
+    }
+    if (fits(p->caps, tot, pass)) {
+        st = launch_on(p, c, imgs, n, d_max, pass, geo, true, stream);
+        if (st != HX_OK) return st;
+    } else {
+        // Consecutive groups that fit, one after another on this context
+        // (each waits for the previous one's table copy before the staging
+        // buffer is rewritten); an image that alone does not fit runs in
+        // the per-image RECOMPUTE form.
+        int i = 0;
+        while (i < n) {
+            ImgWork acc;
+            int j = i;
+            while (j < n) {
+                const ImgWork w = img_work(imgs[j], pass, geo);
+                ImgWork t = acc;
+                t.tiles += w.tiles;
+                t.p2 += w.p2;
+                t.p0 += w.p0;
+                t.code += w.code;
+                if (!fits(p->caps, t, pass)) break;
+                acc = t;
+                ++j;
+            }
+            if (j == i) {
+                st = run_oversized(p, c, imgs[i], d_max ? d_max + i : nullptr, stream);
+                c.last_pass = -1;  // the table no longer matches any batch
+                ++i;
+            } else {
+                st = launch_on(p, c, imgs + i, j - i, d_max ? d_max + i : nullptr, pass, geo,
+                               false, stream);
+                c.last_pass = -1;
+                i = j;
+            }
+            if (st != HX_OK) return st;
+            HX_TRY(hipEventRecord(c.ev_done, stream));
+            c.in_flight = true;
+            if (i < n) {
+                st = ctx_wait(c);
+                if (st != HX_OK) return st;
+            }
+        }
+    }
+    HX_TRY(hipEventRecord(c.ev_done, stream));
+    c.in_flight = true;
     return HX_OK;
 }
 
@@ -487,6 +695,43 @@ static void compute_taps(int ks, double sigma, Taps& t) {
         sum += g[i];
     }
     for (int i = 0; i < kMaxK; ++i) t.g[i] = i < ks ? (float)(g[i] / sum) : 0.0f;
+}
+
+// SRAD's partial sums: 4 doubles per workgroup of one launch, for any
+// image of at most max_pixels pixels (each side at least 1).
+static int64_t srad_part_capacity(int64_t P) {
+    return (P / 8192 + P / 256 + P / 32 + 4) / 4 + 2;
+}
+
+// Everything the pipeline will use, for the forms it was created with.
+static hx_status alloc_scratch(hx_pipeline* p) {
+    MemStats& m = p->mem;
+    const int f = p->prm.forms;
+    p->plane_elems = plane_capacity(p->prm.max_pixels);
+    const size_t pe = (size_t)p->plane_elems;
+    HX_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    HX_TRY(hipEventCreateWithFlags(&p->img_ev, hipEventDisableTiming));
+    HX_TRY(p->slot1.alloc(256, m));
+    if (f & (HX_FORM_IMAGE | HX_FORM_STAGES | HX_FORM_SRAD))
+        HX_TRY(p->planeA.alloc(pe * sizeof(float), m));
+    if (f & (HX_FORM_STAGES | HX_FORM_SRAD)) HX_TRY(p->planeL.alloc(pe * sizeof(float), m));
+    if (f & HX_FORM_STAGES) {
+        HX_TRY(p->planeG2.alloc(pe * sizeof(float), m));
+        HX_TRY(p->planeZ.alloc(pe, m));
+        HX_TRY(p->bufPart.alloc((size_t)kTreeThreads * sizeof(float), m));
+    }
+    if (f & HX_FORM_SRAD)
+        HX_TRY(p->srad_part.alloc(
+            (size_t)srad_part_capacity(p->prm.max_pixels) * 4 * sizeof(double), m));
+    if (f & HX_FORM_BATCH) {
+        p->caps = batch_caps(p->prm, (f & HX_FORM_BATCH_STORE) != 0);
+        p->n_ctx = p->prm.batch_contexts;
+        for (int i = 0; i < p->n_ctx; ++i) {
+            hx_status st = ctx_init(p, p->ctx[i]);
+            if (st != HX_OK) return st;
+        }
+    }
+    return HX_OK;
 }
 
 }  // namespace hx
@@ -520,6 +765,13 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
     if (prm.thresh_frac == 0.0f) prm.thresh_frac = 0.1f;
     if (prm.max_pixels == 0) prm.max_pixels = int64_t(1) << 25;
     if (prm.max_images == 0) prm.max_images = 1024;
+    if (prm.forms == 0) prm.forms = HX_FORM_ALL;
+    if (prm.batch_contexts == 0) prm.batch_contexts = 4;
+    if ((prm.forms & ~HX_FORM_ALL) != 0)
+        return fail(HX_E_INVALID, "forms 0x%x has unknown bits", prm.forms);
+    if (prm.batch_contexts < 1 || prm.batch_contexts > hx_pipeline::kMaxContexts)
+        return fail(HX_E_INVALID, "batch_contexts %d not in 1..%d", prm.batch_contexts,
+                    hx_pipeline::kMaxContexts);
     if (prm.ksize < 1 || prm.ksize > kMaxK || prm.ksize % 2 == 0)
         return fail(HX_E_INVALID, "ksize %d must be odd in 1..%d", prm.ksize, kMaxK);
     if (!(prm.sigma > 0.0f) || !std::isfinite(prm.sigma))
@@ -528,6 +780,8 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
         return fail(HX_E_INVALID, "thresh_frac must be in [0, 1]");
     if (prm.max_pixels < 1 || prm.max_images < 1 || prm.max_images > (1 << 20))
         return fail(HX_E_INVALID, "max_pixels and max_images must be positive");
+    if (prm.max_pixels > (int64_t(1) << 31))
+        return fail(HX_E_INVALID, "max_pixels %lld above 2^31", (long long)prm.max_pixels);
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) return fail(HX_E_HIP, "no HIP device available");
@@ -550,14 +804,7 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
     }
     DeviceGuard g(device);
     (void)hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, device);
-    e = hipMalloc(&p->slot1, 64);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        hx_status st = hip_fail(e, "pipeline allocation");
-        hx_pipeline_destroy(p);
-        return st;
-    }
-    hx_status st = ctx_init(p, p->ctx[0]);
+    hx_status st = alloc_scratch(p);
     if (st != HX_OK) {
         hx_pipeline_destroy(p);
         return st;
@@ -571,18 +818,25 @@ void hx_pipeline_destroy(hx_pipeline* p) {
     DeviceGuard g(p->device);
     (void)hipDeviceSynchronize();
     for (auto& c : p->ctx) ctx_release(c);
-    p->code1.release();
-    p->bufB.release();
-    p->bufL.release();
-    p->bufG2.release();
-    p->bufZ.release();
+    p->slot1.release();
+    p->planeA.release();
+    p->planeL.release();
+    p->planeG2.release();
+    p->planeZ.release();
     p->bufPart.release();
-    p->srad_j.release();
-    p->srad_c.release();
     p->srad_part.release();
-    if (p->slot1) (void)hipFree(p->slot1);
+    if (p->img_ev) (void)hipEventDestroy(p->img_ev);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
+}
+
+hx_status hx_pipeline_memory(const hx_pipeline* p, size_t* device_bytes, size_t* pinned_bytes,
+                             uint64_t* allocations) {
+    if (!p) return fail(HX_E_INVALID, "pipeline is NULL");
+    if (device_bytes) *device_bytes = p->mem.device_bytes;
+    if (pinned_bytes) *pinned_bytes = p->mem.pinned_bytes;
+    if (allocations) *allocations = p->mem.allocations;
+    return HX_OK;
 }
 
 hx_status hx_pipeline_sync(hx_pipeline* p) {
@@ -650,7 +904,7 @@ hx_status hx_edge_detect(hx_pipeline* p, const hx_image* img, float* d_max,
     st = validate_schedule(p, s);
     if (st != HX_OK) return st;
     DeviceGuard g(p->device);
-    return run_image(p, img, d_max, s, stream);
+    return run_image_ordered(p, img, d_max, s, stream);
 }
 
 hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
@@ -677,15 +931,24 @@ hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs, int32_t n
         // Only the stage kernels exist for this blur size: run per image.
         for (int i = 0; i < n; ++i) {
             const hx_schedule s = choose_schedule(p, imgs[i].height, imgs[i].width);
-            hx_status st = run_image(p, &imgs[i], d_max ? d_max + i : nullptr, s, stream);
+            hx_status st =
+                run_image_ordered(p, &imgs[i], d_max ? d_max + i : nullptr, s, stream);
             if (st != HX_OK) return st;
         }
         return HX_OK;
     }
-    int pass = kBatchPass;
+    // The pass structure and tile height: fixed at creation or forced, else
+    // the batch autotuner's for this batch's class, else the default.
+    int pass = 0, ty = 0;
     if (p->prm.pass_mode) pass = p->prm.pass_mode;
-    if (p->forced && p->forced_sched.fusion_depth == 4) pass = p->forced_sched.pass_mode;
-    return run_batched(p, imgs, n, d_max, pass, stream);
+    if (p->forced && p->forced_sched.fusion_depth == 4) {
+        pass = p->forced_sched.pass_mode;
+        if (p->forced_sched.tile_w == 64 * batch_sweep_c() &&
+            p->forced_sched.tile_h >= kBatchTyMin && p->forced_sched.tile_h <= kBatchTyMax &&
+            p->forced_sched.tile_h % 8 == 0)
+            ty = p->forced_sched.tile_h;
+    }
+    return run_batched(p, imgs, n, d_max, pass, ty, stream);
 }
 
 hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img, float* d_B,
@@ -697,17 +960,22 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img, float* d_B,
     DeviceGuard g(p->device);
     hx_schedule s{64, 16, 1, HX_PASS_STORE, HX_REDUCE_TREE};
     if (p->forced && p->forced_sched.fusion_depth == 1) s = p->forced_sched;
-    st = run_image(p, img, d_max, s, stream);
+    st = img_order_begin(p, stream);
     if (st != HX_OK) return st;
-    ImgArgs a = base_args(img, p->slot1, d_max);
-    StageBufs b{};
-    b.op = a.op;
-    b.B = (float*)p->bufB.ptr;
-    b.L = (float*)p->bufL.ptr;
-    b.G2 = (float*)p->bufG2.ptr;
-    b.Z = (uint8_t*)p->bufZ.ptr;
-    HX_TRY(launch_export_stages(a, b, d_B, d_L, d_Z, d_G, stream));
-    return HX_OK;
+    st = run_image(p, img, d_max, s, stream);
+    if (st == HX_OK) {
+        ImgArgs a = base_args(img, (uint32_t*)p->slot1.ptr, d_max);
+        StageBufs b{};
+        b.op = a.op;
+        b.B = (float*)p->planeA.ptr;
+        b.L = (float*)p->planeL.ptr;
+        b.G2 = (float*)p->planeG2.ptr;
+        b.Z = (uint8_t*)p->planeZ.ptr;
+        hipError_t e = launch_export_stages(a, b, d_B, d_L, d_Z, d_G, stream);
+        if (e != hipSuccess) st = hip_fail(e, "launch_export_stages");
+    }
+    hx_status st2 = img_order_end(p, stream);
+    return st != HX_OK ? st : st2;
 }
 
 hx_status hx_srad(hx_pipeline* p, float* d_J, int64_t height, int64_t width, int64_t pitch,
@@ -724,21 +992,30 @@ hx_status hx_srad(hx_pipeline* p, float* d_J, int64_t height, int64_t width, int
     if (niter < 0) return fail(HX_E_INVALID, "niter %d is negative", niter);
     if (!(lambda == lambda) || lambda < 0.0f || lambda > 4.0f)
         return fail(HX_E_INVALID, "lambda %g not in [0, 4]", (double)lambda);
+    if (!has_form(p, HX_FORM_SRAD))
+        return fail(HX_E_UNSUPPORTED, "the pipeline was created without HX_FORM_SRAD scratch");
+    if (plane_need(height, width) > p->plane_elems)
+        return fail(HX_E_UNSUPPORTED, "a %lldx%lld image needs planes of %lld elements; the "
+                    "pipeline's hold %lld (raise max_pixels)", (long long)height,
+                    (long long)width, (long long)plane_need(height, width),
+                    (long long)p->plane_elems);
+    if (srad_blocks(height, width) > srad_part_capacity(p->prm.max_pixels))
+        return fail(HX_E_UNSUPPORTED, "SRAD partial sums exceed the pipeline's capacity");
     DeviceGuard g(p->device);
     const int64_t pb = (width + 3) & ~int64_t(3);
-    const size_t plane = (size_t)height * (size_t)pb * sizeof(float);
-    HX_TRY(p->srad_j.ensure(plane));
-    if (!fused) HX_TRY(p->srad_c.ensure(plane));
-    HX_TRY(p->srad_part.ensure((size_t)srad_blocks(height, width) * 4 * sizeof(double)));
-    float* jb = (float*)p->srad_j.ptr;
-    HX_TRY(launch_srad(d_J, jb, pitch, pb, fused ? nullptr : (float*)p->srad_c.ptr, pb,
-                       (double*)p->srad_part.ptr, d_q0sqr,
-                       (int)height, (int)width, niter, lambda, fused != 0, stream));
-    if (niter % 2 == 1)
-        HX_TRY(hipMemcpy2DAsync(d_J, (size_t)pitch * sizeof(float), jb, (size_t)pb * sizeof(float),
-                                (size_t)width * sizeof(float), (size_t)height,
-                                hipMemcpyDeviceToDevice, stream));
-    return HX_OK;
+    hx_status st = img_order_begin(p, stream);
+    if (st != HX_OK) return st;
+    float* jb = (float*)p->planeA.ptr;
+    hipError_t e = launch_srad(d_J, jb, pitch, pb, fused ? nullptr : (float*)p->planeL.ptr, pb,
+                               (double*)p->srad_part.ptr, d_q0sqr, (int)height, (int)width,
+                               niter, lambda, fused != 0, stream);
+    if (e == hipSuccess && niter % 2 == 1)
+        e = hipMemcpy2DAsync(d_J, (size_t)pitch * sizeof(float), jb,
+                             (size_t)pb * sizeof(float), (size_t)width * sizeof(float),
+                             (size_t)height, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) st = hip_fail(e, "SRAD launch");
+    hx_status st2 = img_order_end(p, stream);
+    return st != HX_OK ? st : st2;
 }
 
 }  // extern "C"

@@ -29,6 +29,7 @@ struct SpecTile {
     float* code;     // C floats per entry
     int32_t* row;
     uint32_t n;
+    uint32_t cap;    // entries the tile may write; n may exceed it
 };
 
 // One image as the kernels see it.  Pitches are in elements of the
@@ -46,6 +47,11 @@ struct ImgArgs {
     uint32_t* slot;   // max G^2 bits of this image
     float* dmax;      // optional: receives M = sqrt(max G^2)
     int32_t H, W;
+    // Batched SPECULATE: the image's pass-1 tile t lists its pixels in
+    // entries [list_base + t * list_cap, list_base + (t + 1) * list_cap).
+    uint32_t list_base, list_cap;
+    // Batched calls: rows per sweep tile of this image (a multiple of 8).
+    int32_t ty;
 };
 
 // Geometry of a register-sweep tile (one wave64): C input columns per lane,
@@ -120,9 +126,10 @@ struct BatchHeader {
     float theta;
     int32_t n_items0;   // SPECULATE: sampled-band items of pass 0
     int32_t pad[2];
-    // SPECULATE: the listed pixels of pass-1 item k occupy entries
-    // [k * 64 * TY, (k + 1) * 64 * TY) of cand_code / cand_row, and
-    // cand_n[k] counts them.
+    // SPECULATE: the listed pixels of pass-1 item k (a tile of image i)
+    // occupy the image's entries for that tile (ImgArgs::list_base and
+    // list_cap) of cand_code / cand_row, and cand_n[k] counts them; a tile
+    // that set more pixels than its capacity is redone whole by pass 2.
     float* cand_code;
     int32_t* cand_row;
     uint32_t* cand_n;
@@ -149,7 +156,11 @@ __host__ __device__ inline int sample_stride(int64_t H) {
     return (int)(f < q ? f : q);
 }
 int64_t batch_sample_items(int ks, int64_t H, int64_t W);
-int64_t batch_spec_entries();  // 64 * TY
+// SPECULATE: listed-pixel capacity of each pass-1 tile of an image with
+// `tiles` tiles: one entry per 16 of the image's pixels, spread evenly.
+inline uint32_t spec_tile_cap(int64_t H, int64_t W, int64_t tiles) {
+    return (uint32_t)((H * W) / (16 * tiles));
+}
 int batch_sweep_c();   // columns per lane of the batch sweep
 int batch_sweep_ty();  // rows per batch sweep tile
 // Rows per pass-2 item of the STORE threshold for width W.

@@ -35,35 +35,53 @@ struct DeviceGuard {
     }
 };
 
-// A device buffer that grows on demand (growth frees and reallocates,
-// which waits for the device; it happens only the first time a larger
-// size is needed).
+// A device or pinned host buffer of the pipeline.  Every one is allocated
+// by hx_pipeline_create (alloc) and released by hx_pipeline_destroy; no
+// call path allocates.  Allocations are counted on the owning pipeline's
+// MemStats.
+struct MemStats {
+    size_t device_bytes = 0, pinned_bytes = 0;
+    uint64_t allocations = 0;
+};
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
-    hipError_t ensure(size_t need);
+    hipError_t alloc(size_t n, MemStats& m);
+    void release();
+};
+struct HostBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t alloc(size_t n, MemStats& m);
     void release();
 };
 
-// Resources of one in-flight batched launch.  Batched calls rotate over a
+// Capacities of one batch context, fixed at creation.
+struct BatchCaps {
+    int64_t items1 = 0, items2 = 0, items0 = 0;  // work items per pass
+    int64_t list_entries = 0;                    // SPECULATE listing
+    size_t table_bytes = 0;
+    int64_t code_elems = 0;                      // STORE code plane (0: none)
+};
+
+// Resources of one in-flight batched launch.  Batched calls pick one of a
 // few of these so launches on different streams never share scratch.
 struct BatchContext {
     bool ready = false;
-    DevBuf table;               // device descriptor table (grows on demand)
-    void* h_table = nullptr;    // pinned staging copy of the table
-    size_t h_table_bytes = 0;
-    uint32_t* slots = nullptr;  // max_images max slots
-    void* spec_state = nullptr; // SPECULATE: max_images bounds, the epoch
-    DevBuf code;                // pass-1 store buffer
+    DevBuf table;               // device descriptor table
+    HostBuf h_table;            // pinned staging copy of the table
+    DevBuf slots;               // max_images max slots
+    DevBuf spec_state;          // SPECULATE: max_images bounds, the epoch
+    DevBuf code;                // pass-1 store buffer (STORE batches)
     DevBuf cand_code, cand_row, cand_n;  // SPECULATE: listed pixels
     hipEvent_t ev_done = nullptr;
     hipEvent_t ev_t[5] = {};    // timing mode
     bool in_flight = false;
+    uint64_t last_use = 0;      // the pipeline's call counter at the last use
     // Captured [reset, (pass 0,) pass 1, pass 2] per pass mode, with the
     // table address and grid sizes baked into the kernel nodes.
     hipGraphExec_t exec[4] = {};
     hipGraph_t graph[4] = {};
-    const void* graph_table[4] = {};
     int64_t graph_items[4][3] = {};  // item counts baked into each graph
     int64_t n_items[3] = {0, 0, 0};  // the table's items of pass 0, 1, 2
     // The call whose table the device copy holds: a repeat of the same
@@ -71,7 +89,24 @@ struct BatchContext {
     std::vector<hx_image> last_imgs;
     float* last_dmax = nullptr;
     int last_pass = -1;
+    int last_ty = 0;
 };
+
+// A batch's class for the batch autotuner: floor(log2) of its total
+// pixels and of its image count.
+struct BatchKey {
+    int px, n;
+    bool operator<(const BatchKey& o) const { return px != o.px ? px < o.px : n < o.n; }
+};
+BatchKey batch_key(const hx_image* imgs, int32_t n);
+// The batched launch's schedule: rows per sweep tile and pass structure.
+struct BatchChoice {
+    int ty = 0;
+    int pass = 0;
+};
+// Tile heights the batched form accepts (multiples of 8 in [kBatchTyMin,
+// kBatchTyMax]) and the ones the batch autotuner tries.
+constexpr int kBatchTyMin = 32, kBatchTyMax = 256;
 
 struct ShapeClass {
     int hb, wb;  // floor(log2(H)), floor(log2(W))
@@ -88,23 +123,34 @@ struct hx_pipeline {
     hx_params prm{};
     hx::Taps taps{};
     int cu_count = 0;
+    hx::MemStats mem;
 
     bool forced = false;
     hx_schedule forced_sched{};
     std::map<hx::ShapeClass, hx_schedule> tuned;
+    std::map<hx::BatchKey, hx::BatchChoice> batch_tuned;  // the batch autotuner's
 
-    // Per-image scratch.
-    uint32_t* slot1 = nullptr;
-    hx::DevBuf code1, bufB, bufL, bufG2, bufZ, bufPart;
-    // SRAD scratch: the second J plane, the c plane (unfused form), the
-    // per-wave partial sums, q0^2.
-    hx::DevBuf srad_j, srad_c, srad_part;
+    // Per-image scratch (forms IMAGE, STAGES, SRAD), one set shared by
+    // every per-image call; plane_elems is each plane's capacity.
+    int64_t plane_elems = 0;
+    hx::DevBuf slot1;
+    hx::DevBuf planeA;   // STORE code / B / SRAD's second J plane
+    hx::DevBuf planeL;   // L / SRAD's c plane
+    hx::DevBuf planeG2, planeZ, bufPart;
+    hx::DevBuf srad_part;
+    // Ordering of per-image calls: each records img_ev on its stream; a
+    // call on another stream waits for it first.
+    hipEvent_t img_ev = nullptr;
+    hipStream_t img_stream = nullptr;
+    bool img_used = false;
 
     // Batched launches.
-    static constexpr int kContexts = 6;
-    hx::BatchContext ctx[kContexts];
-    int next_ctx = 0;
-    std::mutex batch_mu;  // guards context rotation (the server calls from
+    static constexpr int kMaxContexts = 8;
+    int n_ctx = 0;
+    hx::BatchCaps caps;
+    hx::BatchContext ctx[kMaxContexts];
+    uint64_t use_clock = 0;
+    std::mutex batch_mu;  // guards context choice (the server calls from
                           // its own thread)
     hipStream_t capture_stream = nullptr;
     bool timing = false;
@@ -123,15 +169,19 @@ hx_status validate_image(const hx_pipeline* p, const hx_image* img);
 // and the autotuner).
 hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
                     const hx_schedule& s, hipStream_t stream);
+// run_image ordered after the previous per-image call (see img_ev).
+hx_status run_image_ordered(hx_pipeline* p, const hx_image* img, float* d_max,
+                            const hx_schedule& s, hipStream_t stream);
 // Pass structure of batched calls unless one is fixed: SPECULATE reads
 // the input about 1.1 times (once, plus the sampled bands) and measured
 // fastest on the 64 x 1920x1080 batch (0.30 ms per step against 0.36 ms
 // for RECOMPUTE and 0.46 ms for STORE).
 constexpr int kBatchPass = HX_PASS_SPECULATE;
 
-// The batched form with an explicit pass mode.
+// The batched form.  pass_mode / ty 0: the batch autotuner's choice for
+// the batch's class, else SPECULATE / the default tile height.
 hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
-                      float* d_max, int pass_mode, hipStream_t stream);
+                      float* d_max, int pass_mode, int ty, hipStream_t stream);
 // Wait for a context's last launch.
 hx_status ctx_wait(BatchContext& c);
 

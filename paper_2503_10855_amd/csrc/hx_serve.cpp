@@ -16,9 +16,11 @@
 //   poll     hands the mask and the latency (completion minus the
 //            request's scheduled arrival) to the caller.
 // Requests that arrive while others are on the device are admitted as
-// memory frees up and launched in the next batch.  Batches use the
-// RECOMPUTE pass structure, so the pipeline's own scratch stays small and
-// the budget covers the request buffers.
+// memory frees up and launched in the next batch.  Batches run the
+// pipeline's batched form (SPECULATE); its scratch -- batch contexts with
+// their tables and listing stores -- was allocated when the pipeline was
+// created, and the HBM budget covers it too: the arena may hold request
+// buffers only up to the budget less the pipeline's device bytes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,7 +225,7 @@ void launch_batch(hx_server* s, std::unique_lock<std::mutex>& lk, int k,
         e = hipMemcpyAsync(const_cast<float*>(imgs[i].src), s->host + batch[i]->host_off,
                            batch[i]->in_bytes(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        rc = run_batched(s->p, imgs.data(), (int32_t)imgs.size(), nullptr, kBatchPass, st);
+        rc = run_batched(s->p, imgs.data(), (int32_t)imgs.size(), nullptr, 0, 0, st);
     for (size_t i = 0; i < batch.size() && e == hipSuccess && rc == HX_OK; ++i)
         e = hipMemcpyAsync(s->host + batch[i]->host_off + align_up(batch[i]->in_bytes()),
                            imgs[i].mask, batch[i]->mask_bytes(), hipMemcpyDeviceToHost, st);
@@ -318,7 +320,14 @@ hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp, void* d_are
     if (sp->max_batch < 1) return fail(HX_E_INVALID, "max_batch must be positive");
     if (p->prm.ksize != 3 && p->prm.ksize != 5 && p->prm.ksize != 7)
         return fail(HX_E_UNSUPPORTED, "serving needs ksize 3, 5 or 7");
-    const size_t budget = std::min(sp->hbm_budget, arena_bytes);
+    if (!(p->prm.forms & HX_FORM_BATCH))
+        return fail(HX_E_UNSUPPORTED, "serving needs a pipeline with HX_FORM_BATCH scratch");
+    // The pipeline's own device memory counts against the budget.
+    const size_t own = p->mem.device_bytes;
+    if (sp->hbm_budget <= own + 4 * kAlign)
+        return fail(HX_E_INVALID, "HBM budget %zu bytes does not exceed the pipeline's own "
+                    "%zu bytes of scratch", sp->hbm_budget, own);
+    const size_t budget = std::min(sp->hbm_budget - own, arena_bytes);
     if (budget < 4 * kAlign) return fail(HX_E_INVALID, "HBM budget too small");
     std::unique_ptr<hx_server> s(new (std::nothrow) hx_server());
     if (!s) return fail(HX_E_NOMEM, "host allocation failed");

@@ -6,6 +6,7 @@
 // operation order is fixed), so the choice is purely a matter of speed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -80,6 +81,24 @@ std::vector<hx_schedule> candidates(int ks) {
     return c;
 }
 
+// Batch candidates: tile heights x pass structures (STORE only where the
+// pipeline holds its code planes).
+std::vector<BatchChoice> batch_candidates(const hx_pipeline* p) {
+    std::vector<BatchChoice> c;
+    std::vector<int> passes = {HX_PASS_SPECULATE, HX_PASS_RECOMPUTE};
+    if (p->prm.forms & HX_FORM_BATCH_STORE) passes.push_back(HX_PASS_STORE);
+    for (int pass : passes)
+        for (int ty : {32, 48, 64, 72, 80, 96, 112, 128, 160})
+            c.push_back(BatchChoice{ty, pass});
+    return c;
+}
+
+bool parse_batch_entry(const char* line, int* ks, BatchKey* k, BatchChoice* c) {
+    return std::sscanf(line, " {\"batch\": {\"ksize\": %d, \"px_log2\": %d, \"n_log2\": %d, "
+                             "\"tile_h\": %d, \"pass\": %d",
+                       ks, &k->px, &k->n, &c->ty, &c->pass) == 5;
+}
+
 // Minimal reader for the cache lines this file writes.
 bool parse_entry(const char* line, int* ks, int* hb, int* wb, hx_schedule* s) {
     return std::sscanf(line,
@@ -139,12 +158,12 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char*
     for (const hx_schedule& c : candidates(p->prm.ksize)) {
         if (validate_schedule(p, c) != HX_OK) continue;
         // One warm-up call (allocates scratch), then the fastest of three.
-        st = run_image(p, &im, nullptr, c, s);
+        st = run_image_ordered(p, &im, nullptr, c, s);
         if (st != HX_OK) break;
         float ms_min = 1e30f;
         for (int r = 0; r < 3 && st == HX_OK; ++r) {
             e = hipEventRecord(e0, s);
-            if (e == hipSuccess) st = run_image(p, &im, nullptr, c, s);
+            if (e == hipSuccess) st = run_image_ordered(p, &im, nullptr, c, s);
             if (e == hipSuccess && st == HX_OK) e = hipEventRecord(e1, s);
             if (e == hipSuccess && st == HX_OK) e = hipEventSynchronize(e1);
             float ms = 0.0f;
@@ -195,6 +214,97 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width, const char*
     return HX_OK;
 }
 
+hx_status hx_autotune_batch(hx_pipeline* p, const hx_image* imgs, int32_t n,
+                           const char* cache_path, int32_t* tile_h, int32_t* pass_mode) {
+    if (!p || !imgs) return fail(HX_E_INVALID, "NULL argument");
+    if (n < 1 || n > p->prm.max_images)
+        return fail(HX_E_INVALID, "n = %d not in 1..max_images", n);
+    if (!(p->prm.forms & HX_FORM_BATCH))
+        return fail(HX_E_UNSUPPORTED, "the pipeline was created without HX_FORM_BATCH scratch");
+    if (p->prm.ksize != 3 && p->prm.ksize != 5 && p->prm.ksize != 7)
+        return fail(HX_E_UNSUPPORTED, "the batched sweep needs ksize 3, 5 or 7");
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        hx_status st = validate_image(p, &imgs[i]);
+        if (st != HX_OK) return st;
+        total += imgs[i].height * imgs[i].width;
+    }
+    if (total > p->prm.max_pixels) return fail(HX_E_INVALID, "batch exceeds max_pixels");
+    DeviceGuard g(p->device);
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto cleanup = [&]() {
+        if (s) (void)hipStreamDestroy(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "batch autotune setup");
+    }
+    const BatchKey key = batch_key(imgs, n);
+    struct Trial {
+        BatchChoice c;
+        float ms;
+    };
+    std::vector<Trial> trials;
+    BatchChoice best{};
+    float best_ms = 1e30f;
+    hx_status st = HX_OK;
+    for (const BatchChoice& c : batch_candidates(p)) {
+        // Two untimed calls (the first builds the table, the second
+        // captures the graph), then the median of five replays.
+        for (int r = 0; r < 2 && st == HX_OK; ++r)
+            st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, s);
+        std::vector<float> ms;
+        for (int r = 0; r < 5 && st == HX_OK; ++r) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, s);
+            if (e == hipSuccess && st == HX_OK) e = hipEventRecord(e1, s);
+            if (e == hipSuccess && st == HX_OK) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess && st == HX_OK) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) st = hip_fail(e, "batch autotune timing");
+            ms.push_back(t);
+        }
+        if (st != HX_OK) break;
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        trials.push_back({c, med});
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
+        }
+    }
+    e = hipStreamSynchronize(s);
+    cleanup();
+    if (st != HX_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    if (best_ms >= 1e30f) return fail(HX_E_UNSUPPORTED, "no batch schedule could run");
+    p->batch_tuned[key] = best;
+    if (tile_h) *tile_h = best.ty;
+    if (pass_mode) *pass_mode = best.pass;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(HX_E_INVALID, "cannot open autotune cache %s", cache_path);
+        for (const Trial& t : trials)
+            std::fprintf(f,
+                         "{\"batch_trial\": {\"ksize\": %d, \"px_log2\": %d, \"n_log2\": %d, "
+                         "\"tile_h\": %d, \"pass\": %d, \"ms\": %.5f, \"pixels\": %lld, "
+                         "\"images\": %d}}\n",
+                         p->prm.ksize, key.px, key.n, t.c.ty, t.c.pass, t.ms, (long long)total, n);
+        std::fprintf(f,
+                     "{\"batch\": {\"ksize\": %d, \"px_log2\": %d, \"n_log2\": %d, "
+                     "\"tile_h\": %d, \"pass\": %d, \"ms\": %.5f}}\n",
+                     p->prm.ksize, key.px, key.n, best.ty, best.pass, best_ms);
+        std::fclose(f);
+    }
+    return HX_OK;
+}
+
 hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path) {
     if (!p || !cache_path) return fail(HX_E_INVALID, "NULL argument");
     FILE* f = std::fopen(cache_path, "r");
@@ -203,6 +313,16 @@ hx_status hx_autotune_load(hx_pipeline* p, const char* cache_path) {
     int loaded = 0;
     while (std::fgets(line, sizeof line, f)) {
         int ks, hb, wb;
+        BatchKey bk{};
+        BatchChoice bc{};
+        if (parse_batch_entry(line, &ks, &bk, &bc)) {
+            if (ks == p->prm.ksize && bc.ty >= kBatchTyMin && bc.ty <= kBatchTyMax &&
+                bc.ty % 8 == 0 && bc.pass >= HX_PASS_STORE && bc.pass <= HX_PASS_SPECULATE) {
+                p->batch_tuned[bk] = bc;
+                ++loaded;
+            }
+            continue;
+        }
         hx_schedule s{};
         if (!parse_entry(line, &ks, &hb, &wb, &s) || ks != p->prm.ksize) continue;
         if (validate_schedule(p, s) != HX_OK) continue;

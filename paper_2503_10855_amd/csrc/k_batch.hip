@@ -37,7 +37,7 @@ namespace hx {
 #define HX_SWEEP_WAVES 3
 #endif
 constexpr int kBC = HX_BATCH_C;    // columns per lane of the batch sweep
-constexpr int kBTY = HX_BATCH_TY;  // rows per sweep tile
+constexpr int kBTY = HX_BATCH_TY;  // default rows per sweep tile
 
 int batch_sweep_c() { return kBC; }
 int batch_sweep_ty() { return kBTY; }
@@ -58,8 +58,6 @@ int64_t batch_sample_items(int ks, int64_t H, int64_t W) {
     const int st = sample_stride(H);
     return g.strips(W) * ((H + st - 1) / st);
 }
-
-int64_t batch_spec_entries() { return 64 * kBTY; }
 
 // The bound's threshold is scaled down by this factor so that it stays at
 // or below the true max's threshold even if the square root were not
@@ -104,7 +102,7 @@ __device__ __forceinline__ int global_wave() {
 template <int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
-    using S = SweepShape<KS, kBC, kSampleRows, SM_MAXONLY>;
+    using S = SweepShape<KS, kBC, SM_MAXONLY>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
     const uint64_t ep = (uint64_t)*as_global(tv.hdr.epoch) << 32;
@@ -114,9 +112,9 @@ void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
         if (it.local == 0 && lane_id() == 0) *as_global(a.slot) = 0u;
         const int nstrips = (a.W + S::OW - 1) / S::OW;
         float gmax = 0.0f;
-        sweep_tile<KS, kBC, kSampleRows, SM_MAXONLY>(
-            a, tp, (it.local % nstrips) * S::OW, (it.local / nstrips) * sample_stride(a.H), 0.0f,
-            gmax);
+        sweep_tile<KS, kBC, SM_MAXONLY>(a, tp, (it.local % nstrips) * S::OW,
+                                         (it.local / nstrips) * sample_stride(a.H), kSampleRows,
+                                         0.0f, gmax);
         gmax = wave_max(gmax);
         if (lane_id() == 0)
             atomicMax(tv.hdr.bound + it.image,
@@ -130,7 +128,7 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
     constexpr int M1 = PASS == HX_PASS_STORE       ? SM_STORE
                        : PASS == HX_PASS_SPECULATE ? SM_SPEC
                                                    : SM_MAXONLY;
-    using S = SweepShape<KS, kBC, kBTY, M1>;
+    using S = SweepShape<KS, kBC, M1>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
     for (int k = global_wave(); k < tv.hdr.n_items1; k += nw) {
@@ -139,7 +137,7 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
         const int nstrips = (a.W + S::OW - 1) / S::OW;
         float gmax = 0.0f;
         float thr2 = 0.0f;
-        SpecTile sp{nullptr, nullptr, 0u};
+        SpecTile sp{nullptr, nullptr, 0u, 0u};
         if constexpr (PASS == HX_PASS_SPECULATE) {
             // Pass 0 finished before this kernel began, and nothing writes
             // the bounds meanwhile.  (Reading the image's slot, which the
@@ -149,12 +147,13 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
             const uint32_t lb2 = (uint32_t)(bv >> 32) == *as_global(tv.hdr.epoch)
                                      ? (uint32_t)bv : 0u;
             thr2 = thr2_from(lb2, tv.hdr.theta) * kSpecSafety;
-            const int64_t base = (int64_t)k * (64 * kBTY);
+            const int64_t base = (int64_t)a.list_base + (int64_t)it.local * a.list_cap;
             sp.code = tv.hdr.cand_code + base * kBC;
             sp.row = tv.hdr.cand_row + base;
+            sp.cap = a.list_cap;
         }
-        sweep_tile<KS, kBC, kBTY, M1>(a, tp, (it.local % nstrips) * S::OW,
-                                      (it.local / nstrips) * kBTY, thr2, gmax, &sp);
+        sweep_tile<KS, kBC, M1>(a, tp, (it.local % nstrips) * S::OW,
+                                (it.local / nstrips) * a.ty, a.ty, thr2, gmax, &sp);
         if constexpr (PASS == HX_PASS_SPECULATE)
             if (lane_id() == 0) as_global(tv.hdr.cand_n)[k] = sp.n;
         gmax = wave_max(gmax);
@@ -180,7 +179,7 @@ void k_batch_p1s(const uint8_t* __restrict__ table, Taps tp) {
 template <int KS, int PASS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
-    using S = SweepShape<KS, kBC, kBTY, SM_MASK>;
+    using S = SweepShape<KS, kBC, SM_MASK>;
     const TableView tv = view(table);
     const int nw = gridDim.x * 4;
     const int lane = lane_id();
@@ -207,14 +206,22 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
             // the max is final.
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             const int x0 = (it.local % nstrips) * S::OW;
-            const int y0 = (it.local / nstrips) * kBTY;
+            const int y0 = (it.local / nstrips) * a.ty;
             const int n = n_listed;
             // The last reader of this batch's bounds has finished: advance
             // the epoch for the next batch on this context.
             if (k == 0 && lane == 0) *as_global(tv.hdr.epoch) += 1u;
+            if ((uint32_t)n > a.list_cap) {
+                // The tile set more pixels than its share of the listing
+                // holds (its list is incomplete): redo the whole tile's mask
+                // against the true threshold.
+                float unused = 0.0f;
+                sweep_tile<KS, kBC, SM_MASK>(a, tp, x0, y0, a.ty, thr2, unused);
+                continue;
+            }
             const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &
                               ((a.mp % 4) == 0);
-            const int64_t base = (int64_t)k * (64 * kBTY);
+            const int64_t base = (int64_t)a.list_base + (int64_t)it.local * a.list_cap;
             for (int t = lane; t < n; t += 64) {
                 const int64_t idx = base + t;
                 const gptr<const VecF<kBC>> q =
@@ -256,8 +263,8 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
         } else {
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             float unused = 0.0f;
-            sweep_tile<KS, kBC, kBTY, SM_MASK>(a, tp, (it.local % nstrips) * S::OW,
-                                               (it.local / nstrips) * kBTY, thr2, unused);
+            sweep_tile<KS, kBC, SM_MASK>(a, tp, (it.local % nstrips) * S::OW,
+                                         (it.local / nstrips) * a.ty, a.ty, thr2, unused);
         }
     }
 }

@@ -16,7 +16,7 @@ HX_DECL_K(7)
 
 bool sweep_supported(int ks, int c, int ty) {
     return (ks == 3 || ks == 5 || ks == 7) && (c == 1 || c == 2 || c == 4) &&
-           (ty == 16 || ty == 32 || ty == 64 || ty == 128);
+           ty >= 8 && ty <= 256 && ty % 8 == 0;
 }
 
 hipError_t launch_sweep(int mode, int ks, int c, int ty, const ImgArgs& a,

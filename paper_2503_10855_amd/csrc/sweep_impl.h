@@ -10,14 +10,24 @@
 //   B  finishes the vertical blur B(v-R) from the last k Bh rows, and its
 //      row pieces (e+w sums, Sobel dx and sy),
 //   C  forms L and G^2 of row v-R-1 from the last three B rows, and the
-//      horizontal 3-max / 3-min of L,
-//   D  forms Z of row v-R-2 from three max/min rows and emits its output.
+//      signs of L as one 64-bit lane mask per column,
+//   D  forms Z of row v-R-2 from three rows of sign masks and emits its
+//      output.
 // The first 2R+4 steps fill this pipeline and are unrolled with
-// compile-time stage flags; the remaining TY steps run as a loop unrolled
-// by the ring period P = 8 (which divides TY), so every ring slot is a
-// fixed register and the steady state has no stage conditions.  Every
-// value is computed by the helpers in hx_device.h, in the same order as
-// the depth-1 stage kernels, so all schedules agree bit for bit.
+// compile-time stage flags; the remaining `ty` steps (the tile height, a
+// run-time multiple of the ring period P = 8) run as a loop unrolled by P,
+// so every ring slot is a fixed register and the steady state has no stage
+// conditions.  Every value is computed by the helpers in hx_device.h, in
+// the same order as the depth-1 stage kernels, so all schedules agree bit
+// for bit.
+//
+// Stage D works on lane masks, i.e. on the scalar unit: a column's signs of
+// L over the wave are one ballot, the 3x3 window's "holds an L > 0" and
+// "holds only L > 0" are ORs and ANDs of three rows of masks and of the
+// masks of the neighbouring columns (a neighbouring lane's column is the
+// mask shifted by one bit), and the mask bit of a pixel is that window test
+// ANDed with the vector compare G^2 > thr2 -- one v_cmp per column for the
+// signs, one per column for the threshold, one v_cndmask per output byte.
 //
 // Tiles whose whole input window lies inside the image (the common case)
 // run an instantiation with no border logic at all.  The others run one
@@ -27,6 +37,10 @@
 // row 0 exists (before any valid output reads it); columns -- the input
 // column is clamped, and the B and L values of columns outside the image
 // are replaced by the first / last real column's value.
+//
+// Addresses: a row's base address is wave-uniform (scalar registers) and
+// each lane adds a 32-bit unsigned byte offset, so loads and stores use the
+// scalar-base form and no per-lane 64-bit address arithmetic.
 #pragma once
 
 #include <utility>
@@ -35,14 +49,13 @@
 
 namespace hx {
 
-template <int KS, int C, int TY, int MODE>
+template <int KS, int C, int MODE>
 struct SweepShape {
     static constexpr int R = KS / 2;
     static constexpr int HX = R + 2;                       // chain halo
     static constexpr int HL = ((HX + C - 1) / C) * C;      // left halo
     static constexpr int SW = 64 * C;                      // strip width
     static constexpr int OW = ((SW - HL - HX) / C) * C;    // output width
-    static constexpr int NS = TY + 2 * HX;                 // steps
     static constexpr int NP = 2 * R + 4;                   // pipeline fill
     static constexpr int P = 8;                            // ring period
 #ifndef HX_SWEEP_PF
@@ -55,9 +68,12 @@ struct SweepShape {
         MODE == SM_STORE || MODE == SM_MASK || MODE == SM_SPEC;
     static constexpr bool DO_MAX = MODE != SM_MASK;
     static constexpr bool EAGER = MODE == SM_MAXONLY;  // see the steady state
-    static_assert(TY % P == 0, "tile height must be a multiple of the ring period");
     static_assert(KS <= P, "the horizontal-blur ring must hold k rows");
+    static_assert(NP == 2 * HX, "a tile's steps are its rows plus both halos");
 };
+
+// Tile heights are multiples of the ring period.
+constexpr int kSweepRowStep = 8;
 
 template <int C>
 struct alignas(4 * C) VecF {
@@ -71,6 +87,9 @@ template <class F, int... Is>
 __device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, Is...>) {
     (f(IC<Is>{}), ...);
 }
+
+// One bit per lane (bit i = lane i), held in scalar registers.
+using lmask = uint64_t;
 
 // Value held by lane (self + Q); lanes whose source is outside the wave
 // read 0 (those values only ever feed halo columns that are discarded).
@@ -89,11 +108,86 @@ __device__ __forceinline__ float lane_fetch(float v) {
     else return lane_fetch<Q + 1>(dpp_from_left(v));
 }
 
+// 1 if l > 0, else 0 (for finite l): the bits of l as a signed integer,
+// clamped to [0, 1] in one instruction.
+__device__ __forceinline__ uint32_t pos_bit(float l) {
+    uint32_t r;
+    asm("v_med3_i32 %0, %1, 0, 1" : "=v"(r) : "v"(l));
+    return r;
+}
+
 __device__ __forceinline__ float max3f(float a, float b, float c) {
     return __builtin_fmaxf(__builtin_fmaxf(a, b), c);
 }
-__device__ __forceinline__ float min3f(float a, float b, float c) {
-    return __builtin_fminf(__builtin_fminf(a, b), c);
+
+// A uniform pointer plus a per-lane 32-bit unsigned byte offset (the
+// listing's scattered stores).
+template <class T, class B>
+__device__ __forceinline__ gptr<T> at_off(gptr<B> base, uint32_t byte_off) {
+    return (gptr<T>)((gptr<char>)base + byte_off);
+}
+
+// Rows [row0, row0 + rows) of a pitched plane as a buffer resource: each
+// access is the resource (scalar registers), a per-lane byte offset within
+// the row (a vector register fixed for the tile) and the row's byte offset
+// (a scalar register), so no address arithmetic runs per lane.  The
+// resource's extent ends at element `width` of the last row: an access
+// outside it reads 0 / is dropped instead of touching other memory.
+struct RowSpan {
+    __amdgpu_buffer_rsrc_t r;
+    int row0;
+    uint32_t pitch_bytes;
+    __device__ __forceinline__ RowSpan(const void* base, int row0_, int rows,
+                                       int64_t pitch_elems, int elem_bytes, int width) {
+        row0 = row0_;
+        pitch_bytes = (uint32_t)(pitch_elems * elem_bytes);
+        const char* p = (const char*)base + (int64_t)row0_ * pitch_elems * elem_bytes;
+        const uint32_t extent =
+            (uint32_t)(rows - 1) * pitch_bytes + (uint32_t)width * (uint32_t)elem_bytes;
+        // Word 3 of a gfx9 buffer resource: 32-bit data format, the rest 0.
+        r = __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)extent, 0x00020000);
+    }
+    __device__ __forceinline__ uint32_t soff(int row) const {
+        return (uint32_t)(row - row0) * pitch_bytes;
+    }
+};
+
+template <int C>
+__device__ __forceinline__ void span_load(const RowSpan& sp, int row, uint32_t voff,
+                                          float (&dst)[C]) {
+    if constexpr (C == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 v = __builtin_bit_cast(
+            f4, __builtin_amdgcn_raw_buffer_load_b128(sp.r, voff, sp.soff(row), 0));
+        dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+    } else if constexpr (C == 2) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 v = __builtin_bit_cast(
+            f2, __builtin_amdgcn_raw_buffer_load_b64(sp.r, voff, sp.soff(row), 0));
+        dst[0] = v.x; dst[1] = v.y;
+    } else {
+        dst[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(sp.r, voff, sp.soff(row), 0));
+    }
+}
+__device__ __forceinline__ float span_load1(const RowSpan& sp, int row, uint32_t voff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(sp.r, voff, sp.soff(row), 0));
+}
+template <int C>
+__device__ __forceinline__ void span_store(const RowSpan& sp, int row, uint32_t voff,
+                                           const float (&val)[C]) {
+    if constexpr (C == 4) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        const u4 v = {__float_as_uint(val[0]), __float_as_uint(val[1]),
+                      __float_as_uint(val[2]), __float_as_uint(val[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(v, sp.r, voff, sp.soff(row), 0);
+    } else if constexpr (C == 2) {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        const u2 v = {__float_as_uint(val[0]), __float_as_uint(val[1])};
+        __builtin_amdgcn_raw_buffer_store_b64(v, sp.r, voff, sp.soff(row), 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(val[0]), sp.r, voff,
+                                              sp.soff(row), 0);
+    }
 }
 
 // Replace the values of columns outside [0, W) with column 0's / W-1's.
@@ -126,24 +220,43 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
     }
 }
 
-// Run one tile: output columns [x0, x0+OW) x rows [y0, y0+TY), clipped to
-// the image.  BX / BY: the tile's input window crosses a column / row
-// border of the image.  thr2 is used by SM_MASK and SM_SPEC only.  gmax
-// accumulates G^2 over real image pixels of the tile (per lane; the caller
-// reduces).  sp: SM_SPEC's list of the pixels it set.
-template <int KS, int C, int TY, int MODE, bool BX, bool BY>
+// Run one tile: output columns [x0, x0+OW) x rows [y0, y0+ty), clipped to
+// the image; ty is a multiple of kSweepRowStep.  BX / BY: the tile's input
+// window crosses a column / row border of the image; BX also serves images
+// whose rows are not aligned for the vector accesses (it reads and writes
+// one element at a time).  thr2 is used by
+// SM_MASK and SM_SPEC only.  gmax accumulates G^2 over real image pixels
+// of the tile (per lane; the caller reduces).  sp: SM_SPEC's list of the
+// pixels it set; entries beyond sp->cap are counted but not written.
+template <int KS, int C, int MODE, bool BX, bool BY>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
-                                           int x0, int y0, float thr2,
+                                           int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp) {
-    using S = SweepShape<KS, C, TY, MODE>;
+    using S = SweepShape<KS, C, MODE>;
     constexpr int R = S::R, HX = S::HX, HL = S::HL, SW = S::SW, OW = S::OW;
-    constexpr int NS = S::NS, NP = S::NP, P = S::P, PF = S::PF;
+    constexpr int NP = S::NP, P = S::P, PF = S::PF;
+
+    // The blur taps in vector registers: the scalar registers are kept for
+    // the lane masks of stage D and the buffer resources.
+    Taps tv;
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        float g = tp.g[i];
+        asm("" : "+v"(g));
+        tv.g[i] = g;
+    }
 
     const int lane = lane_id();
     const int H = a.H, W = a.W;
+    const int NS = ty + 2 * HX;
     const int xs = x0 - HL;
     const int cbase = xs + C * lane;
-    const int ylim = min(y0 + TY, H);
+    // Byte offsets of the lane's first column in an input / mask row.  Only
+    // lanes inside the image (or, in the border variants, with clamped
+    // columns) ever access memory through them.
+    const uint32_t off_in = (uint32_t)cbase * 4u;
+    const uint32_t off_m = (uint32_t)cbase;
+    const int ylim = min(y0 + ty, H);
     const bool lane_out = (cbase >= x0) & (cbase < x0 + OW);
     // Lanes whose every column has a valid G^2 (its neighbourhood lies in
     // the strip); outside the border variants those are all real pixels.
@@ -151,36 +264,43 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     bool ecol[C];
 #pragma unroll
     for (int e = 0; e < C; ++e) ecol[e] = lane_out & (cbase + e < W);
-    const bool vec_ok =
-        ((reinterpret_cast<uintptr_t>(a.src) % (4 * C)) == 0) & ((a.sp % C) == 0);
-    const bool mask_vec =
-        ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
+    // The lanes that own output columns, as a mask (interior tiles).
+    const lmask out_lanes = __ballot(lane_out);
+
+    // The tile's input rows (clamped into the image), output rows.
+    const int in0 = BY ? max(y0 - HX, 0) : y0 - HX;
+    const int in1 = BY ? min(y0 + ty + HX, H) : y0 + ty + HX;
+    const RowSpan src(a.src, in0, in1 - in0, a.sp, 4, W);
+    const int nout = max(ylim - y0, 1);
+    constexpr bool WRITES_MASK = MODE == SM_MASK || MODE == SM_SPEC;
+    constexpr bool WRITES_F = MODE == SM_STORE || MODE == SM_BG || MODE == SM_BGL;
+    constexpr bool WRITES_G = MODE == SM_BG || MODE == SM_BGL;
+    const RowSpan msk(WRITES_MASK ? (const void*)a.mask : (const void*)a.src, y0, nout,
+                      WRITES_MASK ? a.mp : 0, 1, W);
+    const RowSpan fo(WRITES_F ? (const void*)a.fout : (const void*)a.src, y0, nout,
+                     WRITES_F ? a.op : 0, 4, W);
+    const RowSpan go(WRITES_G ? (const void*)a.g2 : (const void*)a.src, y0, nout,
+                     WRITES_G ? a.op : 0, 4, W);
 
     auto load_row = [&](int v, float (&dst)[C]) {
         const int row = BY ? clampi(v, 0, H - 1) : v;
-        const gptr<const float> rp = as_global(a.src) + (int64_t)row * a.sp;
-        if (!BX && vec_ok) {
-            const gptr<const VecF<C>> q = (gptr<const VecF<C>>)(rp + cbase);
-#pragma unroll
-            for (int e = 0; e < C; ++e) dst[e] = q->v[e];
+        if constexpr (!BX) {
+            span_load<C>(src, row, off_in, dst);
         } else {
 #pragma unroll
             for (int e = 0; e < C; ++e)
-                dst[e] = rp[BX ? clampi(cbase + e, 0, W - 1) : cbase + e];
+                dst[e] = span_load1(src, row, 4u * (uint32_t)clampi(cbase + e, 0, W - 1));
         }
     };
-    auto store_f = [&](float* base, int row, const float (&val)[C]) {
-        const gptr<float> rp = as_global(base) + (int64_t)row * a.op + cbase;
+    auto store_f = [&](const RowSpan& dst, int row, const float (&val)[C]) {
         if constexpr (!BX) {
-            if (lane_out) {
-                const gptr<VecF<C>> q = (gptr<VecF<C>>)rp;
-#pragma unroll
-                for (int e = 0; e < C; ++e) q->v[e] = val[e];
-            }
+            if (__builtin_amdgcn_inverse_ballot_w64(out_lanes)) span_store<C>(dst, row, off_in, val);
         } else {
 #pragma unroll
             for (int e = 0; e < C; ++e)
-                if (ecol[e]) rp[e] = val[e];
+                if (ecol[e])
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(val[e]), dst.r,
+                                                          off_in + 4u * e, dst.soff(row), 0);
         }
     };
 
@@ -190,10 +310,78 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     float ew[P][C];   // B(x-1) + B(x+1)
     float dx[P][C];   // Sobel dx
     float sy[P][C];   // Sobel sy
-    uint32_t hz[P];   // per row: bit e = the 3-wide window at column e holds
-                      // an L > 0 (bits 0..C-1) / holds only L > 0 (bits 8..)
+    uint32_t hz[P];   // per L row: bit e = the 3-wide window at column e
+                      // holds an L > 0 (bits 0..C-1) / holds only L > 0
+                      // (bits 8..8+C-1)
     float g2d[C];     // G^2 of the row waiting for its Z
     float gacc = 0.0f;
+    // The output row of stage D is written one step later, after the next
+    // row's L and G^2 (flush_out): its stores are guarded by the lanes that
+    // own output columns and, for SM_SPEC, the listing is a branch taken
+    // only when the row set a bit.  Each of those ends a basic block, so
+    // deferring them lets a row's zero-crossing work on the scalar unit share
+    // a block with the following row's vector work, and the two overlap.
+    // Pending: the row (vzl, valid if pv), its mask word (mwl) or pass-1
+    // codes (cdl), and for SM_SPEC per column the lanes that set a bit (pl)
+    // with their G^2 (g2l).
+    bool pv = false;
+    int vzl = 0;
+    uint32_t mwl = 0;
+    uint32_t mbl = 0;   // SM_SPEC: the pending row's set columns (bit e)
+    lmask bal = 0;      // SM_SPEC: the lanes of the pending row that set one
+    float cdl[C];
+    float g2l[C];
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        cdl[e] = 0.0f;
+        g2l[e] = 0.0f;
+    }
+    // The lane's columns inside the image, as a nibble (border variants).
+    uint32_t emask = 0;
+#pragma unroll
+    for (int e = 0; e < C; ++e) emask |= ecol[e] ? (1u << e) : 0u;
+    auto flush_out = [&]() {
+        if constexpr (S::NEED_Z) {
+            if (pv) {
+                if constexpr (MODE == SM_STORE) {
+                    store_f(fo, vzl, cdl);
+                } else {
+                    if constexpr (!BX && C == 4) {
+                        if (__builtin_amdgcn_inverse_ballot_w64(out_lanes))
+                            __builtin_amdgcn_raw_buffer_store_b32(mwl, msk.r, off_m,
+                                                                  msk.soff(vzl), 0);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < C; ++e)
+                            if (ecol[e])
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (uint8_t)((mwl >> (8 * e)) & 1u), msk.r, off_m + e,
+                                    msk.soff(vzl), 0);
+                    }
+                }
+                if constexpr (MODE == SM_SPEC) {
+                    // The lanes that set a bit in the row, packed in lane
+                    // order after the tile's earlier entries: their C values
+                    // of G^2, and row | lane | set columns.
+                    if (bal) {
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        const uint32_t idx = sp->n + below;
+                        if ((((bal >> lane) & 1u) != 0u) & (idx < sp->cap)) {
+                            const gptr<VecF<C>> q =
+                                at_off<VecF<C>>(as_global(sp->code), idx * (uint32_t)(4 * C));
+#pragma unroll
+                            for (int e = 0; e < C; ++e) q->v[e] = g2l[e];
+                            *at_off<int32_t>(as_global(sp->row), idx * 4u) = (int32_t)(
+                                ((uint32_t)(vzl - y0) << 10) | ((uint32_t)lane << 4) | mbl);
+                        }
+                        sp->n += (uint32_t)__builtin_popcountll(bal);
+                    }
+                }
+                pv = false;
+            }
+        }
+    };
 
     // One step; J = s mod P, DB/DC/DD: stages B, C, D are active; LD: the
     // step prefetches input row v + PF (every step but the last PF): 1
@@ -219,7 +407,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 ext[kk + R] = lane_fetch<q>(pf[J][kk - q * C]);
             }, std::make_integer_sequence<int, C + 2 * R>{});
 #pragma unroll
-            for (int e = 0; e < C; ++e) bh[J][e] = blur_chain<KS>(&ext[e], tp);
+            for (int e = 0; e < C; ++e) bh[J][e] = blur_chain<KS>(&ext[e], tv);
         }
 
         // ---- B: vertical blur, row vb = v - R
@@ -231,7 +419,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 float col[KS];
 #pragma unroll
                 for (int i = 0; i < KS; ++i) col[i] = bh[(J - 2 * R + i + 4 * P) % P][e];
-                b[e] = blur_chain<KS>(col, tp);
+                b[e] = blur_chain<KS>(col, tv);
             }
             if constexpr (BY) {
                 if (vb >= H) {
@@ -288,8 +476,8 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
             const bool row_out = (vl >= y0) & (vl < ylim);
             if constexpr (MODE == SM_BG) {
                 if (row_out) {
-                    store_f(a.fout, vl, bb[J1]);
-                    store_f(a.g2, vl, g2);
+                    store_f(fo, vl, bb[J1]);
+                    store_f(go, vl, g2);
                 }
             }
             if constexpr (S::NEED_L) {
@@ -299,107 +487,71 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                     l[e] = lap_from(bb[J2][e] + bb[J][e], ew[J1][e], bb[J1][e]);
                 if constexpr (MODE == SM_BGL) {
                     if (row_out) {
-                        store_f(a.fout, vl, l);
-                        store_f(a.g2, vl, g2);
+                        store_f(fo, vl, l);
+                        store_f(go, vl, g2);
                     }
                 }
                 if constexpr (S::NEED_Z) {
                     if constexpr (BX) fix_cols<C, HL, SW>(l, x0, xs, cbase, W);
-                    // Z needs only the sign of L: whether the 3x3 window
-                    // holds an L > 0 (its max is > 0) and whether it holds
-                    // only L > 0 (its min is > 0).  Kept as bits, C per row.
-                    // l > 0 exactly when its bits, read as a signed
-                    // integer, are >= 1 (-0 reads as INT_MIN): clamping
-                    // them to [0, 1] gives the bit without a compare.
-                    uint32_t sg = 0;
+                    // Z needs only the sign of L.  One bit per column (L > 0
+                    // exactly when L's bits, read as a signed integer, are
+                    // >= 1: -0 reads as INT_MIN), laid out with the
+                    // neighbouring lanes' outer columns as a (C+2)-bit
+                    // window: bit 0 the left lane's column C-1, bit e+1
+                    // column e, bit C+1 the right lane's column 0.  Then the
+                    // 3-wide window at each column holds an L > 0 (OR of
+                    // three shifts) / only L > 0 (AND of three shifts).
+                    uint32_t sb[C];
 #pragma unroll
-                    for (int e = 0; e < C; ++e)
-                        sg |= (uint32_t)min(max(__float_as_int(l[e]), 0), 1) << e;
-                    const uint32_t sl = (uint32_t)__builtin_amdgcn_mov_dpp(
-                        (int)sg, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
-                    const uint32_t sr = (uint32_t)__builtin_amdgcn_mov_dpp(
-                        (int)sg, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
-                    // Bit e + 1 of ext is column e; bits 0 and C + 1 the
-                    // neighbouring lanes' edge columns.
-                    const uint32_t ext =
-                        ((sl >> (C - 1)) & 1u) | (sg << 1) | ((sr & 1u) << (C + 1));
-                    constexpr uint32_t CM = (1u << C) - 1u;
-                    hz[J] = ((ext | (ext >> 1) | (ext >> 2)) & CM) |
-                            (((ext & (ext >> 1) & (ext >> 2)) & CM) << 8);
+                    for (int e = 0; e < C; ++e) sb[e] = pos_bit(l[e]);
+                    uint32_t ext = (uint32_t)__builtin_amdgcn_mov_dpp(
+                        (int)sb[C - 1], 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+#pragma unroll
+                    for (int e = 0; e < C; ++e) ext |= sb[e] << (e + 1);
+                    ext |= (uint32_t)__builtin_amdgcn_mov_dpp((int)sb[0], 0x130 /* wave_shl:1 */,
+                                                              0xf, 0xf, true)
+                           << (C + 1);
+                    const uint32_t e1 = ext >> 1, e2 = ext >> 2;
+                    hz[J] = (ext | e1 | e2) | ((ext & e1 & e2) << 8);
                     if constexpr (BY) {
                         if (vl >= H) hz[J] = hz[J1];
                         if (vl == 0) hz[J1] = hz[J];
                     }
+                    flush_out();
                     // ---- D: Z of row vz = vl - 1, and the output
                     if constexpr (DD) {
                         const int vz = vl - 1;
                         if (!BY || ((vz >= y0) & (vz < ylim))) {
+                            // Over the three rows: the window holds an L > 0
+                            // (OR of the low bits) and not only L > 0 (AND of
+                            // the high bits, negated).
+                            constexpr uint32_t CM = (1u << C) - 1u;
                             const uint32_t any = hz[J2] | hz[J1] | hz[J];
                             const uint32_t all = hz[J2] & hz[J1] & hz[J];
                             const uint32_t zb = any & ~(all >> 8) & CM;
                             if constexpr (MODE == SM_STORE) {
-                                float code[C];
 #pragma unroll
                                 for (int e = 0; e < C; ++e)
-                                    code[e] = pass1_code((zb >> e) & 1u, g2d[e]);
-                                store_f(a.fout, vz, code);
+                                    cdl[e] = pass1_code((zb >> e) & 1u, g2d[e]);
                             } else {
                                 static_assert(C <= 4, "one mask byte per column in a word");
-                                const gptr<uint8_t> rp =
-                                    as_global(a.mask) + (int64_t)vz * a.mp + cbase;
-                                // Mask byte e (bit 8e of mw) = Z and G^2 > thr2.
-                                // G^2 > thr2 is the sign of thr2 - G^2 (exact
-                                // for finite values: the difference of two
-                                // different floats is never rounded to 0);
-                                // Z's C bits are spread one per byte by a
-                                // multiply.
-                                uint32_t gw = 0;
+                                // Mask bit e = Z and G^2 > thr2; the word has
+                                // bit e in byte e (a multiply spreads it).
+                                uint32_t gn = 0;
 #pragma unroll
-                                for (int e = 0; e < C; ++e)
-                                    gw |= (__float_as_uint(thr2 - g2d[e]) >> 31) << (8 * e);
-                                const uint32_t mw = gw & ((zb * 0x00204081u) & 0x01010101u);
-                                if (!BX && (C == 4) && mask_vec) {
-                                    if (lane_out) *(gptr<uint32_t>)rp = mw;
-                                } else {
-#pragma unroll
-                                    for (int e = 0; e < C; ++e)
-                                        if (ecol[e]) rp[e] = (uint8_t)((mw >> (8 * e)) & 1u);
-                                }
+                                for (int e = 0; e < C; ++e) gn |= (g2d[e] > thr2) ? (1u << e) : 0u;
+                                const uint32_t mb = zb & gn;
+                                mwl = (mb * 0x00204081u) & 0x01010101u;
                                 if constexpr (MODE == SM_SPEC) {
-                                    // List the lanes that set a bit in this
-                                    // row, packed in lane order after the
-                                    // tile's earlier entries: their C values
-                                    // of G^2, and row | lane | set columns.
-                                    // The multiply gathers byte e's bit into
-                                    // bit 24 + e.
-                                    uint32_t bits = (mw * 0x01020408u) >> 24;
-                                    if constexpr (BX) {
-                                        uint32_t em = 0;
+                                    mbl = BX ? (mb & emask) : mb;
+                                    bal = __ballot(mbl != 0u);
+                                    if constexpr (!BX) bal &= out_lanes;
 #pragma unroll
-                                        for (int e = 0; e < C; ++e) em |= ecol[e] ? (1u << e) : 0u;
-                                        bits &= em;
-                                    } else {
-                                        bits = lane_out ? bits : 0u;
-                                    }
-                                    const uint64_t bal = __ballot(bits != 0u);
-                                    if (bal) {
-                                        if (bits) {
-                                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                                                (uint32_t)(bal >> 32),
-                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                                            const int64_t idx = (int64_t)(sp->n + below);
-                                            const gptr<VecF<C>> q =
-                                                (gptr<VecF<C>>)(as_global(sp->code) + idx * C);
-#pragma unroll
-                                            for (int e = 0; e < C; ++e) q->v[e] = g2d[e];
-                                            as_global(sp->row)[idx] =
-                                                (int32_t)(((uint32_t)(vz - y0) << 10) |
-                                                          ((uint32_t)lane << 4) | bits);
-                                        }
-                                        sp->n += (uint32_t)__builtin_popcountll(bal);
-                                    }
+                                    for (int e = 0; e < C; ++e) g2l[e] = g2d[e];
                                 }
                             }
+                            vzl = vz;
+                            pv = true;
                         }
                     }
 #pragma unroll
@@ -415,9 +567,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     static_for([&](auto st) {
         constexpr int s = decltype(st)::value;
         step(IC<s % P>{}, IC<(s >= 2 * R)>{}, IC<(s >= 2 * R + 2)>{},
-             IC<(s >= 2 * R + 4)>{}, IC<(s + PF < NS)>{}, s);
+             IC<(s >= 2 * R + 4)>{}, IC<1>{}, s);
     }, std::make_integer_sequence<int, NP>{});
-    // Steady state: every stage active, TY steps in groups of P.  With
+    static_assert(NP + PF <= NP + kSweepRowStep, "the fill prefetches within the tile");
+    // Steady state: every stage active, ty steps in groups of P.  With
     // S::EAGER every group but the last prefetches unconditionally, so no
     // load is conditional at run time and the wait before each use allows
     // the full prefetch depth in flight; the heavier modes keep the run-time
@@ -443,26 +596,34 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
             }, std::make_integer_sequence<int, P>{});
         }
     }
+    flush_out();
     if constexpr (!BX && !BY) gacc = gvalid ? gacc : 0.0f;
     gmax = __builtin_fmaxf(gmax, gacc);
 }
 
-template <int KS, int C, int TY, int MODE>
+template <int KS, int C, int MODE>
 __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
-                                           int x0, int y0, float thr2,
+                                           int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp = nullptr) {
-    using S = SweepShape<KS, C, TY, MODE>;
+    using S = SweepShape<KS, C, MODE>;
     const int xs = x0 - S::HL;
-    const bool bx = (xs < 0) | (xs + S::SW > a.W);
-    const bool by = (y0 - S::HX < 0) | (y0 + TY + S::HX > a.H);
+    // Vector rows: input rows that start on 4C-byte boundaries and, for the
+    // mask-writing modes, mask rows that start on 4-byte boundaries.
+    const bool vec_ok =
+        ((reinterpret_cast<uintptr_t>(a.src) % (4 * C)) == 0) & ((a.sp % C) == 0);
+    const bool mask_vec = !(MODE == SM_MASK || MODE == SM_SPEC) ||
+                          (C == 4 && (reinterpret_cast<uintptr_t>(a.mask) % 4) == 0 &&
+                           (a.mp % 4) == 0);
+    const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
+    const bool by = (y0 - S::HX < 0) | (y0 + ty + S::HX > a.H);
     if (!bx & !by)
-        sweep_body<KS, C, TY, MODE, false, false>(a, tp, x0, y0, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, false, false>(a, tp, x0, y0, ty, thr2, gmax, sp);
     else if (!bx)
-        sweep_body<KS, C, TY, MODE, false, true>(a, tp, x0, y0, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, false, true>(a, tp, x0, y0, ty, thr2, gmax, sp);
     else if (!by)
-        sweep_body<KS, C, TY, MODE, true, false>(a, tp, x0, y0, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, true, false>(a, tp, x0, y0, ty, thr2, gmax, sp);
     else
-        sweep_body<KS, C, TY, MODE, true, true>(a, tp, x0, y0, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, true, true>(a, tp, x0, y0, ty, thr2, gmax, sp);
 }
 
 }  // namespace hx

@@ -1,7 +1,7 @@
 // sweep_inst.hip -- instantiates the per-image sweep kernels for one blur
 // size HX_KS and one mode HX_MODE (the build compiles this file once per
-// pair, in parallel) over every tile shape: C in {1,2,4} columns per lane,
-// TY in {16,32,64,128} rows.
+// pair, in parallel) for C in {1,2,4} columns per lane; the tile height is
+// a run-time argument.
 #include "sweep_kernel.h"
 
 #ifndef HX_KS
@@ -19,12 +19,10 @@ namespace hx {
 
 hipError_t HX_FN(int c, int ty, const ImgArgs& a, const Taps& t, float theta,
                  hipStream_t s) {
-#define HX_CASE(C, TY) \
-    if (c == C && ty == TY) return launch_sweep_t<HX_KS, C, TY, HX_MODE>(a, t, theta, s);
-    HX_CASE(1, 16) HX_CASE(1, 32) HX_CASE(1, 64) HX_CASE(1, 128)
-    HX_CASE(2, 16) HX_CASE(2, 32) HX_CASE(2, 64) HX_CASE(2, 128)
-    HX_CASE(4, 16) HX_CASE(4, 32) HX_CASE(4, 64) HX_CASE(4, 128)
-#undef HX_CASE
+    if (!sweep_supported(HX_KS, c, ty)) return hipErrorInvalidValue;
+    if (c == 1) return launch_sweep_t<HX_KS, 1, HX_MODE>(ty, a, t, theta, s);
+    if (c == 2) return launch_sweep_t<HX_KS, 2, HX_MODE>(ty, a, t, theta, s);
+    if (c == 4) return launch_sweep_t<HX_KS, 4, HX_MODE>(ty, a, t, theta, s);
     return hipErrorInvalidValue;
 }
 

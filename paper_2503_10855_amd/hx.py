@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libhx.so")
 HX_OK, HX_E_INVALID, HX_E_NOMEM, HX_E_HIP, HX_E_UNSUPPORTED, HX_E_BUSY, \
     HX_E_PENDING, HX_E_NOT_FOUND = range(8)
 PASS_AUTO, PASS_STORE, PASS_RECOMPUTE, PASS_SPECULATE = 0, 1, 2, 3
+FORM_IMAGE, FORM_STAGES, FORM_BATCH, FORM_BATCH_STORE, FORM_SRAD = 1, 2, 4, 8, 16
+FORM_ALL = 31
 REDUCE_TREE, REDUCE_TWO_LEVEL, REDUCE_SEQUENTIAL = 0, 1, 2
 
 
@@ -26,7 +28,8 @@ class Params(ctypes.Structure):
                 ("thresh_frac", ctypes.c_float), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("fusion_depth", ctypes.c_int32),
                 ("pass_mode", ctypes.c_int32), ("max_pixels", ctypes.c_int64),
-                ("max_images", ctypes.c_int64)]
+                ("max_images", ctypes.c_int64), ("forms", ctypes.c_int32),
+                ("batch_contexts", ctypes.c_int32)]
 
 
 class Image(ctypes.Structure):
@@ -58,6 +61,11 @@ _SIGS = {
     "hx_pipeline_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int,
                                           ctypes.POINTER(_P)]),
     "hx_pipeline_destroy": (None, [_P]),
+    "hx_autotune_batch": (ctypes.c_int, [_P, ctypes.POINTER(Image), _i32, ctypes.c_char_p,
+                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "hx_pipeline_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(_u64)]),
     "hx_pipeline_sync": (ctypes.c_int, [_P]),
     "hx_pipeline_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(Schedule)]),
     "hx_pipeline_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -160,9 +168,9 @@ class Pipeline:
 
     def __init__(self, ksize=5, sigma=1.0, theta=0.1, max_pixels=1 << 25,
                  max_images=1024, device=0, tile_w=0, tile_h=0, fusion_depth=0,
-                 pass_mode=0):
+                 pass_mode=0, forms=0, batch_contexts=0):
         self.params = Params(ksize, sigma, theta, tile_w, tile_h, fusion_depth,
-                             pass_mode, max_pixels, max_images)
+                             pass_mode, max_pixels, max_images, forms, batch_contexts)
         self.device = device
         h = _P()
         _check(_lib.hx_pipeline_create(ctypes.byref(self.params), device,
@@ -177,6 +185,14 @@ class Pipeline:
         if getattr(self, "_h", None):
             _lib.hx_pipeline_destroy(self._h)
             self._h = None
+
+    def memory(self):
+        """(device bytes, pinned host bytes, allocation calls) the pipeline
+        holds; allocation calls stay constant after creation."""
+        d, h, n = ctypes.c_size_t(), ctypes.c_size_t(), _u64()
+        _check(_lib.hx_pipeline_memory(self._h, ctypes.byref(d), ctypes.byref(h),
+                                       ctypes.byref(n)), "hx_pipeline_memory")
+        return d.value, h.value, n.value
 
     def __enter__(self):
         return self
@@ -282,6 +298,20 @@ class Pipeline:
                "hx_autotune")
         return self.schedule(H, W)
 
+    def autotune_batch(self, srcs, masks=None, cache_path=None):
+        """Time the batched call on this batch under every candidate tile
+        height and pass structure; keep the fastest for batches of its class.
+        Returns (tile_h, pass_mode)."""
+        if masks is None:
+            masks = [torch.empty(s.shape, dtype=torch.uint8, device=s.device) for s in srcs]
+        n = len(srcs)
+        arr = (Image * n)(*[image_desc(s, m) for s, m in zip(srcs, masks)])
+        th, pm = _i32(), _i32()
+        _check(_lib.hx_autotune_batch(self._h, arr, n,
+                                      cache_path.encode() if cache_path else None,
+                                      ctypes.byref(th), ctypes.byref(pm)), "hx_autotune_batch")
+        return th.value, pm.value
+
     def autotune_load(self, cache_path):
         _check(_lib.hx_autotune_load(self._h, cache_path.encode()),
                "hx_autotune_load")
@@ -313,8 +343,10 @@ class Server:
     def __init__(self, pipeline: Pipeline, hbm_budget, streams=4, max_batch=64,
                  arena: torch.Tensor = None):
         if arena is None:
-            arena = torch.empty(hbm_budget, dtype=torch.uint8,
-                                device=f"cuda:{pipeline.device}")
+            # The pipeline's own scratch counts against the budget; the arena
+            # holds the rest (hx_serve_create refuses a budget below it).
+            rest = max(hbm_budget - pipeline.memory()[0], 1 << 12)
+            arena = torch.empty(rest, dtype=torch.uint8, device=f"cuda:{pipeline.device}")
         self.arena = arena
         self.pipeline = pipeline
         self.sp = ServeParams(hbm_budget, streams, max_batch)

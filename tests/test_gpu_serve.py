@@ -40,7 +40,8 @@ def test_serve_alone_equals_in_mix(hx):
     sizes = synth.log_uniform_sizes(48, 64, 1024, 77)
     imgs = [synth.image(h, w, 78, i) for i, (h, w) in enumerate(sizes)]
     picks = [0, 17, 40]
-    with hx.Pipeline(theta=THETA, max_pixels=1 << 24, max_images=64) as p:
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 24, max_images=64,
+                     forms=hx.FORM_BATCH) as p:
         alone = {}
         for i in picks:
             with hx.Server(p, hbm_budget=256 << 20, streams=2, max_batch=16) as srv:
@@ -57,7 +58,8 @@ def test_serve_alone_equals_in_mix(hx):
             st = srv.stats()
         print(f"stats {st}", flush=True)
         assert st["completed"] == len(imgs) and st["batches"] >= 2
-        per_image = [p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 24, max_images=64) as q:
+        per_image = [q.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
     for i in picks:
         assert np.array_equal(alone[i], res[i][0]), i
     for i, ((m, lat), ref) in enumerate(zip(res, per_image)):
@@ -70,21 +72,34 @@ def test_serve_alone_equals_in_mix(hx):
 
 
 def test_serve_admission_respects_budget(hx):
-    budget = 3 << 20  # about two 512x512 requests at a time
+    """The budget covers the pipeline's own scratch and the request buffers:
+    with room for about two 512x512 requests beyond the scratch, the peak
+    of the two together stays within it, and a request that could never
+    fit is refused."""
     sizes = [(512, 512)] * 12 + [(300, 700)] * 4
     imgs = [synth.image(h, w, 79, i) for i, (h, w) in enumerate(sizes)]
-    with hx.Pipeline(theta=THETA, max_pixels=1 << 22, max_images=16) as p:
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 20, max_images=16, forms=hx.FORM_BATCH,
+                     batch_contexts=2) as p:
+        own, _, allocs = p.memory()
+        budget = own + (3 << 20)
         with hx.Server(p, hbm_budget=budget, streams=2, max_batch=8) as srv:
-            print("serve under a 3 MiB budget", flush=True)
+            print(f"serve under a budget of {budget} bytes ({own} of pipeline scratch)",
+                  flush=True)
             tickets = [srv.submit(a) for a in imgs]
             res = collect(srv, tickets, sizes)
             st = srv.stats()
-            with pytest.raises(hx.HxError) as ei:
-                srv.submit(np.zeros((2048, 2048), np.float32))
+            with pytest.raises(hx.HxError) as ei:  # 5 MiB: within max_pixels, not the arena
+                srv.submit(np.zeros((1024, 1024), np.float32))
             assert ei.value.status == hx.HX_E_BUSY
-        refs = [p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
+        # A budget that does not exceed the scratch is refused.
+        with pytest.raises(hx.HxError) as ei:
+            hx.Server(p, hbm_budget=own, streams=2, max_batch=8)
+        assert ei.value.status == hx.HX_E_INVALID
+        assert p.memory() == (own, p.memory()[1], allocs)
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 22, max_images=16) as q:
+        refs = [q.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
     print(f"stats {st}", flush=True)
-    assert st["peak_bytes"] <= budget and st["completed"] == len(imgs)
+    assert own + st["peak_bytes"] <= budget and st["completed"] == len(imgs)
     for (m, _), ref in zip(res, refs):
         assert np.array_equal(m, ref)
 
@@ -96,8 +111,10 @@ def test_serve_submit_never_blocks(hx):
     request goes in."""
     side = 2048  # 16 MiB in + 4 MiB mask per request; the pool holds 64 MiB
     imgs = [synth.image(side, side, 80, i) for i in range(5)]
-    with hx.Pipeline(theta=THETA, max_pixels=1 << 23, max_images=4) as p:
-        with hx.Server(p, hbm_budget=48 << 20, streams=2, max_batch=2) as srv:
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 23, max_images=4, forms=hx.FORM_BATCH,
+                     batch_contexts=2) as p:
+        own = p.memory()[0]
+        with hx.Server(p, hbm_budget=own + (48 << 20), streams=2, max_batch=2) as srv:
             print("serve: filling the pinned pool", flush=True)
             tickets = []
             refused = None
@@ -115,8 +132,9 @@ def test_serve_submit_never_blocks(hx):
             res = collect(srv, tickets, shapes)
             t = srv.submit(imgs[refused])
             last = collect(srv, [t], [(side, side)])[0]
-        ref = p.edge_detect(torch.from_numpy(imgs[refused]).cuda()).cpu().numpy()
-        refs = [p.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs[:refused]]
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 23, max_images=4) as q:
+        ref = q.edge_detect(torch.from_numpy(imgs[refused]).cuda()).cpu().numpy()
+        refs = [q.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs[:refused]]
     assert np.array_equal(last[0], ref)
     for (m, _), r in zip(res, refs):
         assert np.array_equal(m, r)

@@ -54,3 +54,39 @@ def test_autotune_choose_persist_reload(hx, tmp_path, ks, sigma):
         q.autotune_load(cache)
         assert tuple(q.schedule(H + 50, W + 100)) == tuple(chosen)  # same shape class
         assert np.array_equal(q.edge_detect(torch.from_numpy(img).cuda()).cpu().numpy(), mask)
+
+
+def test_batch_autotune_choose_persist_reload(hx, tmp_path):
+    """The batch autotuner times every (tile height, pass structure) on the
+    caller's batch, keeps the fastest for the batch's class, writes the
+    trials and the choice, and a pipeline that loads the cache uses it; the
+    masks under the tuned schedule equal the per-image ones and the
+    oracle's."""
+    sizes = [(1080, 1920), (300, 700), (64, 64), (517, 259), (1, 300), (777, 1025)]
+    imgs = [synth.image(h, w, 82, i) for i, (h, w) in enumerate(sizes)]
+    srcs = [torch.from_numpy(a).cuda() for a in imgs]
+    npx = sum(a.size for a in imgs)
+    cache = str(tmp_path / "tune_batch.jsonl")
+    with hx.Pipeline(theta=THETA, max_pixels=npx, max_images=len(sizes)) as p:
+        print("batch autotune", flush=True)
+        th, pm = p.autotune_batch(srcs, cache_path=cache)
+        tuned = [m.cpu().numpy() for m in p.edge_detect_batched(srcs)]
+        per_image = [p.edge_detect(s).cpu().numpy() for s in srcs]
+    lines = [json.loads(x) for x in open(cache)]
+    trials = [x["batch_trial"] for x in lines if "batch_trial" in x]
+    chosen = [x["batch"] for x in lines if "batch" in x]
+    assert len(chosen) == 1 and (chosen[0]["tile_h"], chosen[0]["pass"]) == (th, pm)
+    assert {t["pass"] for t in trials} == {1, 2, 3}
+    assert {t["tile_h"] for t in trials} >= {32, 64, 128}
+    best = min(trials, key=lambda t: t["ms"])
+    assert (best["tile_h"], best["pass"]) == (th, pm)
+    for a, b in zip(tuned, per_image):
+        assert np.array_equal(a, b)
+    for img, m in zip(imgs, tuned):
+        o = oracle.edge_detect(img, 5, 1.0, THETA, stages=True)
+        assert parity.compare_mask(m, o, THETA)["mismatch"] == 0
+    with hx.Pipeline(theta=THETA, max_pixels=npx, max_images=len(sizes)) as q:
+        q.autotune_load(cache)
+        again = [m.cpu().numpy() for m in q.edge_detect_batched(srcs)]
+    for a, b in zip(again, tuned):
+        assert np.array_equal(a, b)
