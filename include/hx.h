@@ -260,6 +260,26 @@ hx_status hx_edge_detect(hx_pipeline* p, const hx_image* img, float* d_max,
 hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs,
                                  int32_t n, float* d_max, hipStream_t stream);
 
+/* For callers that cannot allocate -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation: hx_edge_detect in the
+ * fused STORE form (one sweep writes a code per pixel and the max, a second
+ * kernel thresholds), with its scratch -- the max slot and the pass-1 code
+ * plane -- in one fixed device array of HX_STATIC_SCRATCH_BYTES instead of
+ * the pipeline's buffers.  The call allocates and frees nothing (the
+ * array's device address is looked up once per device, when a pipeline is
+ * created on it).  Each GPU holds its own array for the life of the
+ * process, and every call on that GPU shares it and leaves the last call's
+ * contents there: calls that overlap on one GPU (on different streams, or
+ * from different host threads) race and give undefined masks; calls on one
+ * stream are ordered.  HX_E_INVALID if the image needs more than
+ * HX_STATIC_MAX_ELEMS code elements (H * round_up(W, 4)) or fails the
+ * argument checks of hx_edge_detect; HX_E_UNSUPPORTED for a ksize other
+ * than 3, 5, 7.  The result is bit-identical to hx_edge_detect's. */
+#define HX_STATIC_MAX_ELEMS ((size_t)8 << 20)
+#define HX_STATIC_SCRATCH_BYTES (256 + 4 * HX_STATIC_MAX_ELEMS)
+hx_status hx_edge_detect_static(hx_pipeline* p, const hx_image* img, float* d_max,
+                                hipStream_t stream);
+
 /* Test hook: the fusion-depth-1 pipeline on one image with every stage
  * written out.  d_B, d_L, d_G: dense H*W floats (G is the magnitude);
  * d_Z: dense H*W bytes; d_max: one float (M); the mask goes to img->mask.

@@ -697,6 +697,35 @@ static void compute_taps(int ks, double sigma, Taps& t) {
     for (int i = 0; i < kMaxK; ++i) t.g[i] = i < ks ? (float)(g[i] / sum) : 0.0f;
 }
 
+// Scratch of hx_edge_detect_static: the max slot (first 256 bytes) and the
+// pass-1 code plane, in a fixed array that each device holds once.  Host
+// code never uses the array's name as an address (on the host it is only a
+// stand-in): static_scratch_ptr holds each device's address, looked up with
+// hipGetSymbolAddress while that device is current.
+static __device__ __align__(256) uint8_t scratch[HX_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxDevices];
+
+// Look up (once per device) the static scratch's address on `dev`, which
+// must be the current device.
+static hx_status static_scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HX_E_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_ptr[dev]) return HX_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_static_ptr[dev] = ptr;
+    return HX_OK;
+}
+
+static uint8_t* static_scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    return static_cast<uint8_t*>(g_static_ptr[dev]);
+}
+
 // SRAD's partial sums: 4 doubles per workgroup of one launch, for any
 // image of at most max_pixels pixels (each side at least 1).
 static int64_t srad_part_capacity(int64_t P) {
@@ -805,6 +834,7 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
     DeviceGuard g(device);
     (void)hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     hx_status st = alloc_scratch(p);
+    if (st == HX_OK) st = static_scratch_init(device);
     if (st != HX_OK) {
         hx_pipeline_destroy(p);
         return st;
@@ -905,6 +935,38 @@ hx_status hx_edge_detect(hx_pipeline* p, const hx_image* img, float* d_max,
     if (st != HX_OK) return st;
     DeviceGuard g(p->device);
     return run_image_ordered(p, img, d_max, s, stream);
+}
+
+hx_status hx_edge_detect_static(hx_pipeline* p, const hx_image* img, float* d_max,
+                                hipStream_t stream) {
+    if (!p) return fail(HX_E_INVALID, "pipeline is NULL");
+    hx_status st = validate_image(p, img);
+    if (st != HX_OK) return st;
+    if (!fused_ks(p->prm.ksize))
+        return fail(HX_E_UNSUPPORTED, "the static form needs ksize 3, 5 or 7 (have %d)",
+                    p->prm.ksize);
+    const int64_t need = plane_need(img->height, img->width);
+    if (need > (int64_t)HX_STATIC_MAX_ELEMS)
+        return fail(HX_E_INVALID, "a %lldx%lld image needs %lld code elements; the static "
+                    "scratch holds %lld", (long long)img->height, (long long)img->width,
+                    (long long)need, (long long)HX_STATIC_MAX_ELEMS);
+    uint8_t* base = static_scratch_ptr(p->device);
+    if (!base) return fail(HX_E_HIP, "static scratch of device %d not set up", p->device);
+    // The untuned fused tile: 256 columns, the tallest of 64/32/16 rows that
+    // gives every SIMD a tile.
+    const int64_t simds = 4 * (int64_t)(p->cu_count > 0 ? p->cu_count : 256);
+    const int64_t strips = (img->width + 239) / 240;
+    int th = 64;
+    while (th > 16 && strips * ((img->height + th - 1) / th) < simds) th /= 2;
+    DeviceGuard g(p->device);
+    uint32_t* slot = reinterpret_cast<uint32_t*>(base);
+    ImgArgs a = base_args(img, slot, d_max);
+    a.fout = reinterpret_cast<float*>(base + 256);
+    const float theta = p->prm.thresh_frac;
+    HX_TRY(launch_fill_u32(slot, 0u, 1, stream));
+    HX_TRY(launch_sweep(SM_STORE, p->prm.ksize, 4, th, a, p->taps, theta, stream));
+    HX_TRY(launch_threshold_code(a, theta, stream));
+    return HX_OK;
 }
 
 hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,

@@ -61,6 +61,7 @@ _SIGS = {
     "hx_pipeline_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int,
                                           ctypes.POINTER(_P)]),
     "hx_pipeline_destroy": (None, [_P]),
+    "hx_edge_detect_static": (ctypes.c_int, [_P, ctypes.POINTER(Image), _P, _P]),
     "hx_autotune_batch": (ctypes.c_int, [_P, ctypes.POINTER(Image), _i32, ctypes.c_char_p,
                                          ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "hx_pipeline_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t),
@@ -247,6 +248,18 @@ class Pipeline:
         _check(_lib.hx_edge_detect(self._h, ctypes.byref(d),
                                    dmax.data_ptr() if dmax is not None else None,
                                    _stream(stream)), "hx_edge_detect")
+        return mask
+
+    def edge_detect_static(self, src, mask=None, dmax=None, stream=None):
+        """hx_edge_detect_static: the per-image fused form with its scratch
+        in the library's fixed device array (no allocation; calls that
+        overlap on one GPU race)."""
+        if mask is None:
+            mask = torch.empty(src.shape, dtype=torch.uint8, device=src.device)
+        d = image_desc(src, mask)
+        _check(_lib.hx_edge_detect_static(self._h, ctypes.byref(d),
+                                          dmax.data_ptr() if dmax is not None else None,
+                                          _stream(stream)), "hx_edge_detect_static")
         return mask
 
     def edge_detect_batched(self, srcs, masks=None, dmax=None, stream=None):
