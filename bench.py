@@ -206,12 +206,14 @@ def main():
                     help="untimed steps first (default: 20 in batch mode, 5 otherwise)")
 
     ap.add_argument("--mode", default="batch",
-                    choices=("batch", "serve", "reduce", "tune", "srad"),
+                    choices=("batch", "serve", "reduce", "tune", "tune-batch", "srad"),
                     help="batch: the batched step (default); serve: the continuous-"
                          "batching server under Poisson arrivals; reduce: the "
                          "max-reduction ablation on the unfused per-image form; tune: "
                          "the autotuner's measurement of every schedule on the "
-                         "workload's first image shape; srad: the second workload")
+                         "workload's first image shape; tune-batch: the batch "
+                         "autotuner's trials on the workload's whole batch; srad: the "
+                         "second workload")
     ap.add_argument("--workload", default="batch-64x1080p", choices=sorted(workloads()))
     ap.add_argument("--requests", type=int, default=20000, help="serve: requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -269,6 +271,8 @@ def main():
         return run_reduce(args, hx)
     if args.mode == "tune":
         return run_tune(args, hx)
+    if args.mode == "tune-batch":
+        return run_tune_batch(args, hx)
     if args.mode == "srad":
         return run_srad(args, hx)
 
@@ -734,6 +738,37 @@ def run_tune(args, hx):
                        "sigma": wl.sigma, "schedule_fields": "tile_w, tile_h, fusion_depth, "
                        "pass_mode (1 store, 2 recompute, 3 speculate), reduce_mode"},
             "chosen": list(chosen), "trials": rows}
+    print(json.dumps(line), flush=True)
+
+
+def run_tune_batch(args, hx):
+    """The batch autotuner on the workload's whole batch: every (tile height,
+    pass structure) candidate's median time per batched call, and the
+    choice."""
+    import tempfile
+    import torch
+    wl = workloads()[args.workload]()
+    srcs = [torch.from_numpy(wl.image(i)).cuda() for i in range(len(wl.sizes))]
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune_batch.jsonl")
+        with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=wl.theta,
+                         max_pixels=wl.pixels, max_images=len(srcs)) as p:
+            print(f"tune-batch: {wl.name}", file=sys.stderr, flush=True)
+            th, pm = p.autotune_batch(srcs, cache_path=cache)
+        lines = [json.loads(x) for x in open(cache)]
+    names = {1: "store", 2: "recompute", 3: "speculate"}
+    rows = [{"tile_h": t["tile_h"], "pass": names[t["pass"]], "ms": round(t["ms"], 4),
+             "mpx_s": round(wl.pixels / (t["ms"] * 1e-3) / 1e6, 1),
+             "path_frac": round(PATH_BYTES_PER_PX * wl.pixels / (t["ms"] * 1e-3) / 1e9
+                                / HBM_PEAK_GBS, 4)}
+            for x in lines if "batch_trial" in x for t in [x["batch_trial"]]]
+    rows.sort(key=lambda r: r["ms"])
+    line = {"metric": "batch autotuner sweep (one batched call, median of 5)",
+            "unit": "Mpixel/s", "value": rows[0]["mpx_s"], "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "images": len(srcs), "pixels": wl.pixels,
+                       "ksize": wl.ksize},
+            "chosen": {"tile_h": th, "pass": names[pm]}, "trials": rows}
     print(json.dumps(line), flush=True)
 
 

@@ -280,10 +280,13 @@ hx_status hx_edge_detect_batched(hx_pipeline* p, const hx_image* imgs,
 hx_status hx_edge_detect_static(hx_pipeline* p, const hx_image* img, float* d_max,
                                 hipStream_t stream);
 
-/* Test hook: the fusion-depth-1 pipeline on one image with every stage
- * written out.  d_B, d_L, d_G: dense H*W floats (G is the magnitude);
- * d_Z: dense H*W bytes; d_max: one float (M); the mask goes to img->mask.
- * Any of d_B, d_L, d_Z, d_G may be NULL. */
+/* Test hook: the per-image pipeline at fusion depth 1 (or at the depth 1, 2
+ * or 3 of a forced schedule) on one image, with every stage it keeps in
+ * memory written out.  d_B, d_L, d_G: dense H*W floats (G is the
+ * magnitude); d_Z: dense H*W bytes; d_max: one float (M); the mask goes to
+ * img->mask.  Any of d_B, d_L, d_Z, d_G may be NULL; depth 2 keeps L on
+ * chip and depth 3 keeps B on chip, so d_L (depth 2) / d_B (depth 3) must
+ * be NULL there (HX_E_UNSUPPORTED otherwise). */
 hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img,
                                 float* d_B, float* d_L, uint8_t* d_Z,
                                 float* d_G, float* d_max, hipStream_t stream);

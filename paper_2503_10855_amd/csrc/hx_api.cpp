@@ -1020,8 +1020,14 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img, float* d_B,
     hx_status st = validate_image(p, img);
     if (st != HX_OK) return st;
     DeviceGuard g(p->device);
+    // Depth 1 unless a depth-1, -2 or -3 schedule is forced; depths 2 and 3
+    // keep one stage on chip (L, respectively B), which cannot be exported.
     hx_schedule s{64, 16, 1, HX_PASS_STORE, HX_REDUCE_TREE};
-    if (p->forced && p->forced_sched.fusion_depth == 1) s = p->forced_sched;
+    if (p->forced && p->forced_sched.fusion_depth <= 3) s = p->forced_sched;
+    if (s.fusion_depth == 2 && d_L)
+        return fail(HX_E_UNSUPPORTED, "fusion depth 2 keeps L on chip: pass d_L = NULL");
+    if (s.fusion_depth == 3 && d_B)
+        return fail(HX_E_UNSUPPORTED, "fusion depth 3 keeps B on chip: pass d_B = NULL");
     st = img_order_begin(p, stream);
     if (st != HX_OK) return st;
     st = run_image(p, img, d_max, s, stream);

@@ -100,7 +100,7 @@ hipError_t launch_zero_cross(const ImgArgs& a, const StageBufs& b,
 // also launches the final combining kernel.
 hipError_t launch_sobel_max(const ImgArgs& a, const StageBufs& b, int tw,
                             int th, int reduce_mode, hipStream_t s);
-// Depth-2 second kernel: L from B, then Z.
+// Depth-2 second kernel: L from B, then Z (64 x 16 tiles only).
 hipError_t launch_lap_zero_cross(const ImgArgs& a, const StageBufs& b, int tw,
                                  int th, hipStream_t s);
 // Final threshold of depths 1-3: (Z, G^2, max) -> mask, M into dmax.

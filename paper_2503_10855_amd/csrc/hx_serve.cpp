@@ -41,38 +41,127 @@
 namespace hx {
 namespace {
 
-// Copies `rows` rows of `row_bytes` between pitched host buffers.  A large
-// copy is split into row ranges over up to 8 threads: one thread moves
-// host memory at a fraction of what the memory system sustains, and the
-// biggest requests (a 4096 x 4096 input is 64 MiB) would otherwise hold
-// the caller for milliseconds.
-void copy_rows(void* dst, size_t dst_pitch, const void* src, size_t src_pitch,
-               size_t row_bytes, int64_t rows) {
-    auto part = [=](int64_t r0, int64_t r1) {
+// Host copies of request images into and out of the pinned pool, split by
+// rows over a pool of threads the server starts once: one thread moves
+// host memory at a fraction of what the memory system sustains, a typical
+// request (about 1 Mpx, 4 MB in) would otherwise hold its caller for
+// hundreds of microseconds, and starting threads per copy costs tens of
+// microseconds each.
+class CopyPool {
+   public:
+    explicit CopyPool(int workers) {
+        for (int i = 0; i < workers; ++i) {
+            try {
+                threads_.emplace_back([this] { run(); });
+            } catch (...) {
+                break;  // fewer helpers: the callers copy more themselves
+            }
+        }
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : threads_) t.join();
+    }
+    int helpers() const { return (int)threads_.size(); }
+
+    // Copy rows [0, rows) of row_bytes each; returns when all are copied.
+    void copy(void* dst, size_t dst_pitch, const void* src, size_t src_pitch,
+              size_t row_bytes, int64_t rows) {
+        const size_t total = row_bytes * (size_t)rows;
+        const int64_t parts =
+            std::min<int64_t>({(int64_t)helpers() + 1, rows,
+                               std::max<int64_t>(1, (int64_t)(total / kMinPart))});
+        if (parts <= 1) {
+            copy_part(dst, dst_pitch, src, src_pitch, row_bytes, 0, rows);
+            return;
+        }
+        const int64_t per = (rows + parts - 1) / parts;
+        Latch latch;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (int64_t k = 1; k < parts; ++k) {
+                const int64_t r0 = k * per, r1 = std::min(rows, r0 + per);
+                if (r0 >= r1) continue;
+                ++latch.left;
+                tasks_.push_back(Task{dst, dst_pitch, src, src_pitch, row_bytes, r0, r1, &latch});
+            }
+        }
+        cv_.notify_all();
+        copy_part(dst, dst_pitch, src, src_pitch, row_bytes, 0, std::min(rows, per));
+        // Help with this copy's parts that no helper has taken yet, then wait.
+        for (;;) {
+            Task t;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                auto it = std::find_if(tasks_.begin(), tasks_.end(),
+                                       [&](const Task& x) { return x.latch == &latch; });
+                if (it == tasks_.end()) {
+                    done_cv_.wait(lk, [&] { return latch.left == 0; });
+                    return;
+                }
+                t = *it;
+                tasks_.erase(it);
+            }
+            finish(t);
+        }
+    }
+
+   private:
+    static constexpr size_t kMinPart = size_t(256) << 10;  // bytes per part, at least
+    struct Latch {
+        int64_t left = 0;
+    };
+    struct Task {
+        void* dst;
+        size_t dst_pitch;
+        const void* src;
+        size_t src_pitch, row_bytes;
+        int64_t r0, r1;
+        Latch* latch;
+    };
+    static void copy_part(void* dst, size_t dst_pitch, const void* src, size_t src_pitch,
+                          size_t row_bytes, int64_t r0, int64_t r1) {
+        if (dst_pitch == row_bytes && src_pitch == row_bytes) {
+            std::memcpy(static_cast<char*>(dst) + (size_t)r0 * dst_pitch,
+                        static_cast<const char*>(src) + (size_t)r0 * src_pitch,
+                        (size_t)(r1 - r0) * row_bytes);
+            return;
+        }
         for (int64_t y = r0; y < r1; ++y)
             std::memcpy(static_cast<char*>(dst) + (size_t)y * dst_pitch,
                         static_cast<const char*>(src) + (size_t)y * src_pitch, row_bytes);
-    };
-    const size_t total = row_bytes * (size_t)rows;
-    const int64_t nt = std::min<int64_t>({8, rows, (int64_t)(total / (4u << 20))});
-    if (nt <= 1) {
-        part(0, rows);
-        return;
     }
-    const int64_t per = (rows + nt - 1) / nt;
-    std::vector<std::thread> pool;
-    for (int64_t t = 1; t < nt; ++t) {
-        const int64_t r0 = t * per, r1 = std::min(rows, r0 + per);
-        if (r0 >= r1) continue;
-        try {
-            pool.emplace_back(part, r0, r1);
-        } catch (...) {  // no thread to be had: copy these rows here
-            part(r0, r1);
+    void finish(const Task& t) {
+        copy_part(t.dst, t.dst_pitch, t.src, t.src_pitch, t.row_bytes, t.r0, t.r1);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            --t.latch->left;
+        }
+        done_cv_.notify_all();
+    }
+    void run() {
+        for (;;) {
+            Task t;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || !tasks_.empty(); });
+                if (tasks_.empty()) return;  // stopping
+                t = tasks_.front();
+                tasks_.pop_front();
+            }
+            finish(t);
         }
     }
-    part(0, std::min(rows, per));
-    for (auto& th : pool) th.join();
-}
+    std::vector<std::thread> threads_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Task> tasks_;
+    bool stop_ = false;
+};
 
 constexpr size_t kAlign = 256;
 
@@ -146,6 +235,7 @@ struct Batch;
 
 struct hx_server {
     hx_pipeline* p = nullptr;
+    std::unique_ptr<hx::CopyPool> copies;  // host copies of request images
     hx_serve_params sp{};
     uint8_t* arena = nullptr;
     uint8_t* host = nullptr;  // pinned pool
@@ -353,6 +443,15 @@ hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp, void* d_are
         s->in_flight.push_back(0);
     }
     s->t0 = std::chrono::steady_clock::now();
+    {
+        const unsigned hc = std::thread::hardware_concurrency();
+        s->copies.reset(new (std::nothrow) CopyPool((int)std::min(7u, hc > 1 ? hc - 1 : 0u)));
+        if (!s->copies) {
+            for (auto x : s->streams) (void)hipStreamDestroy(x);
+            (void)hipHostFree(s->host);
+            return fail(HX_E_NOMEM, "host allocation failed");
+        }
+    }
     hx_server* raw = s.get();
     try {
         raw->sched = std::thread(scheduler, raw);
@@ -394,8 +493,8 @@ hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h, int64_t w
     s->reqs.emplace(rp->id, std::move(r));
     lk.unlock();
     // Copy the rows into the pinned pool (the caller may reuse h_src).
-    copy_rows(s->host + rp->host_off, sizeof(float) * (size_t)w, h_src,
-              sizeof(float) * (size_t)pitch, sizeof(float) * (size_t)w, h);
+    s->copies->copy(s->host + rp->host_off, sizeof(float) * (size_t)w, h_src,
+                    sizeof(float) * (size_t)pitch, sizeof(float) * (size_t)w, h);
     lk.lock();
     s->queued.push_back(rp);
     *ticket = rp->id;
@@ -423,8 +522,9 @@ hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
     if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
     if (h_mask) {
         if (mask_pitch < r->w) return fail(HX_E_INVALID, "mask_pitch below width");
-        copy_rows(h_mask, (size_t)mask_pitch, s->host + r->host_off + align_up(r->in_bytes()),
-                  (size_t)r->w, (size_t)r->w, r->h);
+        s->copies->copy(h_mask, (size_t)mask_pitch,
+                        s->host + r->host_off + align_up(r->in_bytes()), (size_t)r->w,
+                        (size_t)r->w, r->h);
     }
     if (latency_s) *latency_s = r->done_t - r->arrival;
     if (service_s) *service_s = r->done_t - r->launch_t;

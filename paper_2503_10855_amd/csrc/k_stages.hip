@@ -98,32 +98,13 @@ __global__ __launch_bounds__(256) void k_zero_cross(ImgArgs a, StageBufs b,
     }
 }
 
-__global__ __launch_bounds__(256) void k_lap_zero_cross(ImgArgs a, StageBufs b,
-                                                       TileMap m) {
-    for (int k = 0; k < reps(m); ++k) {
-        int x, y;
-        if (!tile_px(m, k, a.W, a.H, x, y)) continue;
-        float mx = -__builtin_inff(), mn = __builtin_inff();
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                // L at the clamped neighbour (each stage reads clamped).
-                const int yy = clampi(y + dy, 0, a.H - 1);
-                const int xx = clampi(x + dx, 0, a.W - 1);
-                const float v = lap_at(b.B, b.op, yy, xx, a.H, a.W);
-                mx = __builtin_fmaxf(mx, v);
-                mn = __builtin_fminf(mn, v);
-            }
-        b.Z[(int64_t)y * b.op + x] = zero_cross(mx, mn) ? 1 : 0;
-    }
-}
-
 // Depth 2's second kernel for 64 x 16 output tiles: B of the tile and a
 // 2-pixel halo is staged in LDS once, L of the tile and a 1-pixel halo is
 // computed into LDS once per pixel, and Z reads its 3 x 3 window from LDS
 // (instead of 9 Laplacians of 5 global loads each per pixel).  Every LDS
 // cell holds the stage's value at the clamped image position, so the same
-// operands reach lap_from and zero_cross as in k_lap_zero_cross: the same
-// bits.
+// operands reach lap_from and zero_cross as in the depth-1 Laplacian and
+// zero-crossing kernels: the same bits.
 constexpr int kLzW = 64, kLzH = 16;
 __global__ __launch_bounds__(256) void k_lap_zero_cross_lds(ImgArgs a, StageBufs b,
                                                            TileMap m) {
@@ -351,11 +332,9 @@ hipError_t launch_zero_cross(const ImgArgs& a, const StageBufs& b,
 
 hipError_t launch_lap_zero_cross(const ImgArgs& a, const StageBufs& b, int tw,
                                  int th, hipStream_t s) {
+    if (tw != kLzW || th != kLzH) return hipErrorInvalidValue;  // its one tile shape
     const TileMap m = make_map(a, tw, th);
-    if (tw == kLzW && th == kLzH)
-        hipLaunchKernelGGL(k_lap_zero_cross_lds, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
-    else
-        hipLaunchKernelGGL(k_lap_zero_cross, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
+    hipLaunchKernelGGL(k_lap_zero_cross_lds, dim3(grid_of(m)), dim3(256), 0, s, a, b, m);
     return hipGetLastError();
 }
 

@@ -191,6 +191,12 @@ __device__ __forceinline__ void span_store(const RowSpan& sp, int row, uint32_t 
 }
 
 // Replace the values of columns outside [0, W) with column 0's / W-1's.
+// Columns come in whole lanes on the left (the strip starts at a multiple
+// of C), so the left fix is per lane; on the right, column W-1 is element
+// `el` of lane `ln` (both wave-uniform): every element of that lane is read
+// and one picked with scalar selects.  (Picking the element first with
+// selects on the vector side lets the compiler index the lane's C values
+// as an array in scratch memory, a load and a full memory wait per row.)
 template <int C, int HL, int SW>
 __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
                                          int cbase, int W) {
@@ -200,13 +206,11 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
             __builtin_amdgcn_readlane(__float_as_int(x[0]), HL / C));
 #pragma unroll
         for (int e = 0; e < C; ++e)
-            if (cbase + e < 0) x[e] = v0;
+            if (cbase < 0) x[e] = v0;
     }
     if (xs + SW > W) {
         const int cw = W - 1 - xs;
         const int ln = cw / C, el = cw - ln * C;
-        // Column W-1 is element `el` of lane `ln` (both wave-uniform): read
-        // every element of that lane and pick one with a scalar select.
         int pick = 0;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -266,6 +270,11 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     for (int e = 0; e < C; ++e) ecol[e] = lane_out & (cbase + e < W);
     // The lanes that own output columns, as a mask (interior tiles).
     const lmask out_lanes = __ballot(lane_out);
+    // Border variants: the lanes that may write their mask row as one word
+    // (all C columns inside the image, word-aligned mask rows).
+    const bool mask_words = (C == 4) && ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &&
+                            ((a.mp % 4) == 0);
+    const lmask word_lanes = mask_words ? __ballot(lane_out & (cbase + C <= W)) : 0;
 
     // The tile's input rows (clamped into the image), output rows.
     const int in0 = BY ? max(y0 - HX, 0) : y0 - HX;
@@ -351,12 +360,20 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                             __builtin_amdgcn_raw_buffer_store_b32(mwl, msk.r, off_m,
                                                                   msk.soff(vzl), 0);
                     } else {
+                        // Whole words for the lanes whose C columns are all
+                        // inside the image (when mask rows are word
+                        // aligned), single bytes for the rest.
+                        if (__builtin_amdgcn_inverse_ballot_w64(word_lanes)) {
+                            __builtin_amdgcn_raw_buffer_store_b32(mwl, msk.r, off_m,
+                                                                  msk.soff(vzl), 0);
+                        } else {
 #pragma unroll
-                        for (int e = 0; e < C; ++e)
-                            if (ecol[e])
-                                __builtin_amdgcn_raw_buffer_store_b8(
-                                    (uint8_t)((mwl >> (8 * e)) & 1u), msk.r, off_m + e,
-                                    msk.soff(vzl), 0);
+                            for (int e = 0; e < C; ++e)
+                                if (ecol[e])
+                                    __builtin_amdgcn_raw_buffer_store_b8(
+                                        (uint8_t)((mwl >> (8 * e)) & 1u), msk.r, off_m + e,
+                                        msk.soff(vzl), 0);
+                        }
                     }
                 }
                 if constexpr (MODE == SM_SPEC) {

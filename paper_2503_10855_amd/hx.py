@@ -278,20 +278,22 @@ class Pipeline:
         run() makes the batched call without rebuilding them."""
         return PreparedBatch(self, srcs, masks, dmax)
 
-    def edge_detect_stages(self, src, stream=None):
+    def edge_detect_stages(self, src, stream=None, stages=("B", "L", "Z", "G")):
+        """The stage hook: a dict of device tensors B, L, Z, G (those named in
+        `stages`), M and mask.  Depth 1 by default; under a forced depth-2
+        (depth-3) schedule L (B) is kept on chip and cannot be asked for."""
         H, W = src.shape
         dev = src.device
-        out = dict(B=torch.empty((H, W), dtype=torch.float32, device=dev),
-                   L=torch.empty((H, W), dtype=torch.float32, device=dev),
-                   Z=torch.empty((H, W), dtype=torch.uint8, device=dev),
-                   G=torch.empty((H, W), dtype=torch.float32, device=dev),
-                   M=torch.empty(1, dtype=torch.float32, device=dev),
+        out = dict(M=torch.empty(1, dtype=torch.float32, device=dev),
                    mask=torch.empty((H, W), dtype=torch.uint8, device=dev))
+        for k in stages:
+            out[k] = torch.empty((H, W), dtype=torch.uint8 if k == "Z" else torch.float32,
+                                 device=dev)
         d = image_desc(src, out["mask"])
+        ptr = lambda k: out[k].data_ptr() if k in out else None  # noqa: E731
         _check(_lib.hx_edge_detect_stages(
-            self._h, ctypes.byref(d), out["B"].data_ptr(), out["L"].data_ptr(),
-            out["Z"].data_ptr(), out["G"].data_ptr(), out["M"].data_ptr(),
-            _stream(stream)), "hx_edge_detect_stages")
+            self._h, ctypes.byref(d), ptr("B"), ptr("L"), ptr("Z"), ptr("G"),
+            out["M"].data_ptr(), _stream(stream)), "hx_edge_detect_stages")
         return out
 
     def srad(self, J, niter, lam=0.5, fused=True, q_log=None, stream=None):
