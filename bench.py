@@ -33,6 +33,8 @@ PATH_BYTES_PER_PX = 5.0    # input read once + mask written once
 # touches only the listed pixels.
 KERNEL_BYTES_PER_PX = {1: {1: 4.0, 2: 1.0}, 2: {1: 4.0, 2: 5.0}, 3: {1: 5.0, 2: 0.0}}
 BATCH_DEFAULT_PASS = 3    # the library's pass structure for batched calls
+BATCH_TILE_W = 256        # batched sweep tiles: one wave, 4 columns per lane
+BATCH_DEFAULT_TY = 64     # their height when neither tuned nor fixed
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_64x1080p.json")
 SWEEP_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in
                  ("sweep_impl.h", "hx_device.h", "hx_kernels.h", "k_batch.hip",
@@ -46,7 +48,11 @@ def workloads():
             "band-1024x8192-k7": synth.band_8192}
 
 
-SRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_srad_4096.json")
+def srad_traffic_file(side):
+    """The committed counter summary of SRAD on a side x side image."""
+    return os.path.join(ROOT, "profiles", f"traffic_srad_{side}.json")
+
+
 SRAD_SOURCES = ["paper_2503_10855_amd/csrc/" + f for f in ("k_srad.hip", "srad_kernels.h")]
 
 
@@ -58,15 +64,18 @@ def source_hash(sources=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, pixels, path=TRAFFIC_FILE, sources=None):
+def measured_traffic(kernel, pixels, path=TRAFFIC_FILE, sources=None, tile_h=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when absent or taken on different kernel sources."""
+    summary, or None when absent, taken on different kernel sources, or
+    taken at another sweep tile height than `tile_h` (when both state one)."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != source_hash(sources) or t.get("pixels") != pixels:
+        return None
+    if tile_h is not None and t.get("tile_h") not in (None, tile_h):
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -221,7 +230,7 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="serve: compute streams (default 4); batch: consecutive batches go "
                          "to this many streams in turn, each with its own output buffers "
-                         "(default 2; 1: one stream)")
+                         "(default 4; 1: one stream)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
     ap.add_argument("--srad-side", type=int, default=4096, help="srad: image side")
     ap.add_argument("--srad-iters", type=int, default=100, help="srad: iterations per step")
@@ -233,6 +242,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch: skip the batch autotuner (default tile height and pass)")
+    ap.add_argument("--batch-tile-h", type=int, default=0, metavar="TY",
+                    help="batch: fix the sweep tile height (16..256, a multiple of 8) "
+                         "with --pass-mode's pass structure (SPECULATE if 0); skips "
+                         "the batch autotuner")
     ap.add_argument("--no-serve", action="store_true",
                     help="batch: skip the short serving leg")
     ap.add_argument("--serve-requests", type=int, default=4000,
@@ -248,7 +261,7 @@ def main():
     if args.warmup is None:
         args.warmup = 20 if args.mode == "batch" else 5
     if args.streams is None:
-        args.streams = 2 if args.mode == "batch" else 4
+        args.streams = 4
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); "
@@ -296,7 +309,13 @@ def main():
         # The batched launch's tile height and pass structure, chosen by the
         # batch autotuner on this batch (unless a pass structure is fixed).
         batch_sched = None
-        if not args.no_tune and not args.pass_mode:
+        if args.batch_tile_h:
+            pm_fixed = args.pass_mode or BATCH_DEFAULT_PASS
+            p.set_schedule(BATCH_TILE_W, args.batch_tile_h, 4, pm_fixed)
+            batch_sched = {"tile_h": args.batch_tile_h,
+                           "pass": {1: "store", 2: "recompute", 3: "speculate"}[pm_fixed],
+                           "fixed": True}
+        elif not args.no_tune and not args.pass_mode:
             t0 = time.perf_counter()
             th, pm = p.autotune_batch(srcs, mask_sets[0])
             batch_sched = {"tile_h": th, "pass": {1: "store", 2: "recompute",
@@ -328,6 +347,7 @@ def main():
             acc += np.array(p.last_timing())
         p.set_timing(False)
         ms_reset, ms_p1, ms_p2, ms_p0 = (acc / args.steps).tolist()
+        p.set_schedule()
 
         per_image = None
         if not args.no_per_image:
@@ -383,7 +403,8 @@ def main():
     kname = (f"k_batch_p1s<{wl.ksize}>" if (pm, dom) == (3, 1)
              else f"k_batch_p{dom}<{wl.ksize}, {pm}>")
     achieved = bpp * pixels / (ms_dom * 1e-3) / 1e9
-    traffic = measured_traffic(kname, pixels)
+    traffic = measured_traffic(kname, pixels,
+                               tile_h=batch_sched["tile_h"] if batch_sched else BATCH_DEFAULT_TY)
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -640,15 +661,20 @@ def run_reduce(args, hx):
 
 
 SRAD_BYTES_PER_PX = 8.0   # fused: J read once and written once per iteration
+MALL_BYTES = 256e6        # the MI355X's last-level cache (Infinity Cache)
 
 
 def run_srad(args, hx):
-    """SRAD on one 4096x4096 speckle image, 100 iterations per step: the
-    fused form (timed) and the unfused form, the oracle on the same work.
-    A step restores the input (a device copy, timed separately and
-    subtracted); the per-launch time of the fused kernel is the step's time
-    less that of a zero-iteration step (copy + the initial sums), over the
-    iterations."""
+    """SRAD on one square speckle image (default 4096x4096), 100 iterations
+    per step: the fused form (timed) and the unfused form, the oracle on a
+    bounded number of iterations of the same image.  A step restores the
+    input (a device copy, timed separately and subtracted); the per-launch
+    time of the fused kernel is the step's time less that of a
+    zero-iteration step (copy + the initial sums), over the iterations.
+    The fused kernel reads J and writes the next J (8 B/px per iteration);
+    when those two planes fit in the 256 MB MALL (4096^2: 134 MB) the
+    iterations run out of it, and the line says so: only a size whose planes
+    exceed it (8192^2: 537 MB) measures HBM."""
     import torch
     from paper_2503_10855_amd import synth
 
@@ -675,14 +701,21 @@ def run_srad(args, hx):
     ms_launch = out["fused"][1]
     mpx_it = H * W * niter / (ms_step * 1e-3) / 1e6
     achieved = SRAD_BYTES_PER_PX * H * W / (ms_launch * 1e-3) / 1e9
-    traffic = measured_traffic("k_srad_sweep<0>", H * W, SRAD_TRAFFIC_FILE, SRAD_SOURCES)
+    traffic = measured_traffic("k_srad_sweep<0>", H * W, srad_traffic_file(H), SRAD_SOURCES)
+    working_set = SRAD_BYTES_PER_PX * H * W
+    mall = working_set <= MALL_BYTES
     line = {"metric": "SRAD Mpixel-iterations/s", "value": round(mpx_it, 1),
             "unit": "Mpixel*iter/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
             "data": "synthetic", "vs_baseline": None,
             "config": {"workload": f"srad-{H}x{W}-{niter}iter", "lambda": lam,
-                       "form": "fused (c in registers)"},
+                       "form": "fused (c in registers)",
+                       "working_set_mb": round(working_set / 1e6, 1),
+                       "resident": "MALL (256 MB)" if mall else "HBM"},
             "ms_per_step": round(ms_step, 4),
+            # Priced against the HBM peak either way; a MALL-resident
+            # working set (config.resident) makes that an upper bound on
+            # what HBM delivered, not a measurement of it.
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -694,15 +727,20 @@ def run_srad(args, hx):
             "fused_equals_unfused": same}
     if not args.no_cpu:
         import oracle
-        # The oracle runs the whole workload (about 10 s on one core).
+        # The oracle on the same image for as many of the iterations as fit
+        # in about 10 s on one core (all 100 at 4096^2).
         t0 = time.perf_counter()
-        oracle.srad(img, niter, lam)
+        oracle.srad(img, 1, lam)
+        one = time.perf_counter() - t0
+        n_or = int(max(1, min(niter, 10.0 / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.srad(img, n_or, lam)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(H * W * niter / dt / 1e6, 2),
+        line["cpu_baseline"] = {"value": round(H * W * n_or / dt / 1e6, 2),
                                 "unit": "Mpixel*iter/s", "cores": 1, "kind": "oracle",
                                 "host": host_info(),
-                                "sample": f"the whole workload ({H}x{W}, {niter} "
-                                          f"iterations), {dt:.2f} s"}
+                                "sample": f"{n_or} of the {niter} iterations on the "
+                                          f"{H}x{W} image, {dt:.2f} s"}
     calib_copy(args, line)
     print(json.dumps(line), flush=True)
 
@@ -758,12 +796,14 @@ def run_tune_batch(args, hx):
         lines = [json.loads(x) for x in open(cache)]
     names = {1: "store", 2: "recompute", 3: "speculate"}
     rows = [{"tile_h": t["tile_h"], "pass": names[t["pass"]], "ms": round(t["ms"], 4),
-             "mpx_s": round(wl.pixels / (t["ms"] * 1e-3) / 1e6, 1),
-             "path_frac": round(PATH_BYTES_PER_PX * wl.pixels / (t["ms"] * 1e-3) / 1e9
+             "tput_ms": round(t["tput_ms"], 4), "in_flight": t["in_flight"],
+             "mpx_s": round(wl.pixels / (t["tput_ms"] * 1e-3) / 1e6, 1),
+             "path_frac": round(PATH_BYTES_PER_PX * wl.pixels / (t["tput_ms"] * 1e-3) / 1e9
                                 / HBM_PEAK_GBS, 4)}
             for x in lines if "batch_trial" in x for t in [x["batch_trial"]]]
-    rows.sort(key=lambda r: r["ms"])
-    line = {"metric": "batch autotuner sweep (one batched call, median of 5)",
+    rows.sort(key=lambda r: r["tput_ms"])
+    line = {"metric": "batch autotuner sweep (time per batched call with calls in flight on "
+                      "several streams; ms: one call alone)",
             "unit": "Mpixel/s", "value": rows[0]["mpx_s"], "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": wl.name, "images": len(srcs), "pixels": wl.pixels,

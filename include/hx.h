@@ -75,7 +75,7 @@ typedef struct hx_server hx_server;
  *              the pixels it set, with their G^2; pass 2 re-decides only
  *              those against the true max.  Exact for every input; fast
  *              when the listed pixels are few.  Runs 256-column sweep
- *              tiles of 32..256 rows (a multiple of 8). */
+ *              tiles of 16..256 rows (a multiple of 8). */
 enum { HX_PASS_AUTO = 0, HX_PASS_STORE = 1, HX_PASS_RECOMPUTE = 2,
        HX_PASS_SPECULATE = 3 };
 
@@ -304,11 +304,16 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
 /* The batch autotuner: times the batched call on the caller's batch (imgs,
  * n: as hx_edge_detect_batched; their masks are written, with the same
  * bits as any schedule gives) under every candidate -- sweep tile heights
- * 32..160 rows x pass structures SPECULATE, RECOMPUTE and, when the
- * pipeline holds HX_FORM_BATCH_STORE, STORE; median of five graph replays
- * each -- and keeps the fastest for the batch's class (floor(log2) of its
- * total pixels and of n): later batched calls of that class use it unless
- * the pass structure is fixed or a schedule forced.  Blocking.  Appends one
+ * 16..160 rows x pass structures SPECULATE, RECOMPUTE and, when the
+ * pipeline holds HX_FORM_BATCH_STORE, STORE -- and keeps the one with the
+ * highest throughput for the batch's class (floor(log2) of its total
+ * pixels and of n): the time per call with min(batch_contexts, 4) calls in
+ * flight on as many streams of the tuner's own (median of three runs of 4
+ * calls per stream; the time of one call alone, median of five, is
+ * recorded beside it).  Later batched calls of that class use the choice
+ * unless the pass structure is fixed or a schedule forced.  The calls in
+ * flight all write the caller's masks, with the same bits, so on return
+ * they hold the batch's result.  Blocking.  Appends one
  * {"batch_trial": ...} line per candidate and the chosen {"batch": ...}
  * line to cache_path (NULL = do not persist); *tile_h and *pass_mode
  * (nullable) receive the choice. */
@@ -404,6 +409,15 @@ hx_status hx_serve_stats(const hx_server* s, uint64_t* completed,
 hx_status hx_serve_destroy(hx_server* s);
 
 /* ------------------------------------------------------------ errors --- */
+/* hx_status_str: the status's name.  hx_last_error: the text of the last
+ * failure on the calling thread.  Diagnostics, read from the environment
+ * once per process: HX_LOG=1 prints to stderr every failing call with its
+ * text, pipeline and server creation (sizes, bytes), each batched call's
+ * schedule (images, pixels, pass structure, tile height and its source,
+ * context, groups) and the batch autotuner's trials; HX_LOG=2 adds each
+ * per-image call's schedule, each batch's launch form (graph replay,
+ * capture, direct) and each serving batch.  HX_TRACE=1 brackets API calls
+ * and batch phases in roctx ranges (rocprofv3 --marker-trace). */
 const char* hx_status_str(hx_status s);
 const char* hx_last_error(void);
 

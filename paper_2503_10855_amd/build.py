@@ -26,7 +26,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++20", "-fPIC", "-Wall",
          "-I" + CSRC, "-I" + os.path.join(ROOT, "include")]
 
 PLAIN = ["k_stages.hip", "k_sweep.hip", "k_batch.hip", "hx_api.cpp",
-         "hx_tune.hip", "hx_serve.cpp", "hx_sched.cpp", "k_srad.hip"]
+         "hx_tune.hip", "hx_serve.cpp", "hx_sched.cpp", "k_srad.hip", "hx_log.cpp"]
 SWEEP_KS = (3, 5, 7)
 SWEEP_MODES = (0, 1, 2, 3, 4)
 
@@ -70,7 +70,7 @@ def build(verbose: bool = False, incremental: bool = False, jobs: int = 0) -> st
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda u: _compile(u, incremental, dep_t, verbose), units))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-ldl", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

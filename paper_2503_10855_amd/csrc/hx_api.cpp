@@ -39,6 +39,7 @@ hx_status fail(hx_status st, const char* fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     t_err = buf;
+    logf(1, "error %s: %s", hx_status_str(st), buf);
     return st;
 }
 
@@ -374,10 +375,12 @@ hx_status ctx_wait(BatchContext& c) {
 // for this context on stream s;
 // with `timed`, bracket each launch with the context's timing events
 // (ev_t: 0 reset 1 pass-0 4 pass-1 2 pass-2 3).  Each pass runs one wave
-// per item (workgroups of four waves): a grid sized to the batch measured
-// faster than persistent workgroups striding over the items.
+// per item (batch_wg_waves() waves per workgroup): a grid sized to the
+// batch measured faster than persistent workgroups striding over the
+// items.
 static int phase_grid(const BatchContext& c, int ph) {
-    return (int)std::max<int64_t>(1, (c.n_items[ph] + 3) / 4);
+    const int w = batch_wg_waves();
+    return (int)std::max<int64_t>(1, (c.n_items[ph] + w - 1) / w);
 }
 
 static hipError_t enqueue_phases(hx_pipeline* p, BatchContext& c, int pass, hipStream_t s,
@@ -544,23 +547,34 @@ static hx_status launch_on(hx_pipeline* p, BatchContext& c, const hx_image* imgs
                       c.last_dmax == d_max && c.last_imgs.size() == (size_t)n &&
                       std::memcmp(c.last_imgs.data(), imgs, sizeof(hx_image) * n) == 0;
     if (!same) {
+        TraceRange tr("hx.batch.table");
         hx_status st = build_table(p, c, imgs, n, d_max, pass, geo, stream);
         if (st != HX_OK) return st;
     }
+    TraceRange tr("hx.batch.enqueue");
     // A batch seen again on this context replays a captured graph; a new
     // composition launches its kernels directly (capturing every new batch
     // would cost more than it saves, e.g. when serving).
     static const bool no_graph = std::getenv("HX_NO_GRAPH") != nullptr;
+    const char* how;
     if (p->timing) {
         HX_TRY(enqueue_phases(p, c, pass, stream, true));
         p->last_timed_ctx = (int)(&c - p->ctx);
+        how = "timed launches";
     } else if (no_graph || !same || !allow_graph) {
         HX_TRY(enqueue_phases(p, c, pass, stream));
+        how = "direct launches";
     } else {
+        const bool captured = c.exec[pass] != nullptr &&
+                              std::memcmp(c.graph_items[pass], c.n_items, sizeof c.n_items) == 0;
         hx_status st = ctx_graph(p, c, pass);
         if (st != HX_OK) return st;
         HX_TRY(hipGraphLaunch(c.exec[pass], stream));
+        how = captured ? "graph replay" : "graph capture + launch";
     }
+    logf(2, "batch context %d: %d images, items %lld / %lld / %lld (pass 1 / 2 / 0), %s",
+         (int)(&c - p->ctx), n, (long long)c.n_items[1], (long long)c.n_items[2],
+         (long long)c.n_items[0], how);
     return HX_OK;
 }
 
@@ -576,12 +590,17 @@ BatchKey batch_key(const hx_image* imgs, int32_t n) {
 }
 
 hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
-                      float* d_max, int pass, int ty, hipStream_t stream) {
+                      float* d_max, int pass, int ty, hipStream_t stream, int ctx) {
     const int ks = p->prm.ksize;
+    TraceRange trace("hx.batch");
+    const char* ty_from = ty ? "fixed" : "default";
     {
         auto it = p->batch_tuned.find(batch_key(imgs, n));
         if (it != p->batch_tuned.end()) {
-            if (!ty) ty = it->second.ty;
+            if (!ty) {
+                ty = it->second.ty;
+                ty_from = "tuned";
+            }
             // A tuned STORE needs the STORE plane; without it the default
             // pass structure runs.
             if (!pass && (it->second.pass != HX_PASS_STORE || has_form(p, HX_FORM_BATCH_STORE)))
@@ -625,6 +644,7 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
         if (oldest < 0 || c.last_use < p->ctx[oldest].last_use) oldest = i;
     }
     if (pick < 0) pick = oldest_match >= 0 ? oldest_match : oldest;
+    if (ctx >= 0) pick = ctx % p->n_ctx;
     BatchContext& c = p->ctx[pick];
     c.last_use = ++p->use_clock;
     hx_status st = ctx_wait(c);
@@ -638,6 +658,14 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
         tot.p2 += w.p2;
         tot.p0 += w.p0;
         tot.code += w.code;
+    }
+    static const char* const kPassName[] = {"auto", "STORE", "RECOMPUTE", "SPECULATE"};
+    if (log_level() >= 1) {
+        int64_t px = 0;
+        for (int i = 0; i < n; ++i) px += imgs[i].height * imgs[i].width;
+        logf(1, "batched call: %d images, %lld px, %s, %d-row tiles (%s), context %d%s", n,
+             (long long)px, kPassName[pass], ty, ty_from, pick,
+             fits(p->caps, tot, pass) ? "" : ", split into groups");
     }
     if (fits(p->caps, tot, pass)) {
         st = launch_on(p, c, imgs, n, d_max, pass, geo, true, stream);
@@ -663,6 +691,8 @@ hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
                 ++j;
             }
             if (j == i) {
+                logf(2, "image %d (%lldx%lld) exceeds a batch table: per-image RECOMPUTE", i,
+                     (long long)imgs[i].height, (long long)imgs[i].width);
                 st = run_oversized(p, c, imgs[i], d_max ? d_max + i : nullptr, stream);
                 c.last_pass = -1;  // the table no longer matches any batch
                 ++i;
@@ -839,6 +869,11 @@ hx_status hx_pipeline_create(const hx_params* params, int device, hx_pipeline** 
         hx_pipeline_destroy(p);
         return st;
     }
+    logf(1, "pipeline on device %d: ksize %d, forms 0x%x, %d batch contexts, max_pixels %lld, "
+         "max_images %lld; %zu device bytes, %zu pinned bytes in %llu allocations",
+         device, p->prm.ksize, (unsigned)p->prm.forms, p->n_ctx, (long long)p->prm.max_pixels,
+         (long long)p->prm.max_images, p->mem.device_bytes, p->mem.pinned_bytes,
+         (unsigned long long)p->mem.allocations);
     *out = p;
     return HX_OK;
 }
@@ -933,6 +968,9 @@ hx_status hx_edge_detect(hx_pipeline* p, const hx_image* img, float* d_max,
     const hx_schedule s = choose_schedule(p, img->height, img->width);
     st = validate_schedule(p, s);
     if (st != HX_OK) return st;
+    TraceRange trace("hx.edge_detect");
+    logf(2, "per-image call %lldx%lld: %s", (long long)img->height, (long long)img->width,
+         schedule_text(s).c_str());
     DeviceGuard g(p->device);
     return run_image_ordered(p, img, d_max, s, stream);
 }
@@ -1049,6 +1087,7 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img, float* d_B,
 hx_status hx_srad(hx_pipeline* p, float* d_J, int64_t height, int64_t width, int64_t pitch,
                   int32_t niter, float lambda, int32_t fused, double* d_q0sqr,
                   hipStream_t stream) {
+    TraceRange trace("hx.srad");
     if (!p) return fail(HX_E_INVALID, "pipeline is NULL");
     if (!d_J) return fail(HX_E_INVALID, "d_J is NULL");
     if (height < 1 || width < 1 || pitch < width)

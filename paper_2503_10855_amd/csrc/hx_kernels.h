@@ -162,6 +162,7 @@ inline uint32_t spec_tile_cap(int64_t H, int64_t W, int64_t tiles) {
     return (uint32_t)((H * W) / (16 * tiles));
 }
 int batch_sweep_c();   // columns per lane of the batch sweep
+int batch_wg_waves();  // waves per workgroup of the batch pass kernels
 int batch_sweep_ty();  // rows per batch sweep tile
 // Rows per pass-2 item of the STORE threshold for width W.
 int batch_p2_rows(int64_t W);

@@ -23,6 +23,18 @@ hx_status compile_schedule(const char* text, hx_schedule* out);
 std::string schedule_text(const hx_schedule& s);
 hx_status hip_fail(hipError_t e, const char* what);
 
+// Diagnostics (hx_log.cpp): HX_LOG=<level> prints lines of at most that
+// level to stderr; HX_TRACE=1 turns TraceRange into a roctx range.
+int log_level();
+void logf(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+struct TraceRange {
+    bool on;
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // Make `dev` current for the lifetime of the guard.
 struct DeviceGuard {
     int prev = -1, dev;
@@ -106,7 +118,7 @@ struct BatchChoice {
 };
 // Tile heights the batched form accepts (multiples of 8 in [kBatchTyMin,
 // kBatchTyMax]) and the ones the batch autotuner tries.
-constexpr int kBatchTyMin = 32, kBatchTyMax = 256;
+constexpr int kBatchTyMin = 16, kBatchTyMax = 256;
 
 struct ShapeClass {
     int hb, wb;  // floor(log2(H)), floor(log2(W))
@@ -179,9 +191,13 @@ hx_status run_image_ordered(hx_pipeline* p, const hx_image* img, float* d_max,
 constexpr int kBatchPass = HX_PASS_SPECULATE;
 
 // The batched form.  pass_mode / ty 0: the batch autotuner's choice for
-// the batch's class, else SPECULATE / the default tile height.
+// the batch's class, else SPECULATE / the default tile height.  ctx >= 0
+// runs on that batch context (waiting for its previous batch) instead of
+// the one the context policy picks; the batch autotuner uses it to keep
+// one batch in flight per context.
 hx_status run_batched(hx_pipeline* p, const hx_image* imgs, int32_t n,
-                      float* d_max, int pass_mode, int ty, hipStream_t stream);
+                      float* d_max, int pass_mode, int ty, hipStream_t stream,
+                      int ctx = -1);
 // Wait for a context's last launch.
 hx_status ctx_wait(BatchContext& c);
 

@@ -296,6 +296,7 @@ void set_sticky(hx_server* s, hx_status st) {
 void launch_batch(hx_server* s, std::unique_lock<std::mutex>& lk, int k,
                   std::vector<Request*> batch) {
     hipStream_t st = s->streams[k];
+    TraceRange trace("hx.serve.batch");
     std::vector<hx_image> imgs;
     imgs.reserve(batch.size());
     const double t_launch = now_s(s);
@@ -308,6 +309,7 @@ void launch_batch(hx_server* s, std::unique_lock<std::mutex>& lk, int k,
     }
     s->in_flight[k]++;
     s->batches++;
+    logf(2, "serve: batch of %zu requests on stream %d", batch.size(), k);
     lk.unlock();
     hx_status rc = HX_OK;
     hipError_t e = hipSuccess;
@@ -460,6 +462,9 @@ hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp, void* d_are
         (void)hipHostFree(s->host);
         return fail(HX_E_NOMEM, "could not start the scheduler thread");
     }
+    logf(1, "server: budget %zu bytes (pipeline %zu, arena %zu), %d streams, max batch %d, "
+         "pinned pool %zu bytes, %d copy helpers", sp->hbm_budget, own, budget, sp->streams,
+         sp->max_batch, host_pool, s->copies->helpers());
     *out = s.release();
     return HX_OK;
 }

@@ -88,7 +88,7 @@ std::vector<BatchChoice> batch_candidates(const hx_pipeline* p) {
     std::vector<int> passes = {HX_PASS_SPECULATE, HX_PASS_RECOMPUTE};
     if (p->prm.forms & HX_FORM_BATCH_STORE) passes.push_back(HX_PASS_STORE);
     for (int pass : passes)
-        for (int ty : {32, 48, 64, 72, 80, 96, 112, 128, 160})
+        for (int ty : {16, 24, 32, 48, 64, 72, 80, 96, 112, 128, 160})
             c.push_back(BatchChoice{ty, pass});
     return c;
 }
@@ -230,14 +230,27 @@ hx_status hx_autotune_batch(hx_pipeline* p, const hx_image* imgs, int32_t n,
         total += imgs[i].height * imgs[i].width;
     }
     if (total > p->prm.max_pixels) return fail(HX_E_INVALID, "batch exceeds max_pixels");
+    TraceRange trace("hx.autotune_batch");
     DeviceGuard g(p->device);
-    hipStream_t s = nullptr;
+    // One stream per batch context (at most 4), call k on stream and
+    // context k mod S: the throughput trials keep that many calls in
+    // flight, as a caller feeding batches on several streams does.  All calls write the same masks with the same bits;
+    // after the last one the masks hold the result of any of them.
+    const int S = std::max(1, std::min(p->n_ctx, 4));
+    hipStream_t st_[4] = {};
+    hipEvent_t done_[4] = {};
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
+    hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int i = 0; i < S && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&st_[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done_[i], hipEventDisableTiming);
+    }
     auto cleanup = [&]() {
-        if (s) (void)hipStreamDestroy(s);
+        for (int i = 0; i < S; ++i) {
+            if (st_[i]) (void)hipStreamDestroy(st_[i]);
+            if (done_[i]) (void)hipEventDestroy(done_[i]);
+        }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
@@ -245,46 +258,83 @@ hx_status hx_autotune_batch(hx_pipeline* p, const hx_image* imgs, int32_t n,
         cleanup();
         return hip_fail(e, "batch autotune setup");
     }
+    hipStream_t s = st_[0];
     const BatchKey key = batch_key(imgs, n);
     struct Trial {
         BatchChoice c;
-        float ms;
+        float ms;       // one call alone: median of five
+        float tput_ms;  // per call with S calls in flight: median of three runs
     };
     std::vector<Trial> trials;
     BatchChoice best{};
     float best_ms = 1e30f;
     hx_status st = HX_OK;
+    // Elapsed ms between e0 and e1 once e1 has completed.
+    auto elapsed = [&](float* t) {
+        e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(t, e0, e1);
+        if (e != hipSuccess) st = hip_fail(e, "batch autotune timing");
+    };
     for (const BatchChoice& c : batch_candidates(p)) {
-        // Two untimed calls (the first builds the table, the second
-        // captures the graph), then the median of five replays.
-        for (int r = 0; r < 2 && st == HX_OK; ++r)
-            st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, s);
+        // Untimed: three calls per stream (each context builds its table,
+        // captures its graph and replays it).
+        for (int r = 0; r < 3 * S && st == HX_OK; ++r)
+            st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, st_[r % S], r % S);
+        for (int i = 0; i < S && st == HX_OK; ++i)
+            if ((e = hipStreamSynchronize(st_[i])) != hipSuccess)
+                st = hip_fail(e, "batch autotune warm-up");
         std::vector<float> ms;
         for (int r = 0; r < 5 && st == HX_OK; ++r) {
             e = hipEventRecord(e0, s);
-            if (e == hipSuccess) st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, s);
+            if (e == hipSuccess) st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, s, 0);
             if (e == hipSuccess && st == HX_OK) e = hipEventRecord(e1, s);
-            if (e == hipSuccess && st == HX_OK) e = hipEventSynchronize(e1);
             float t = 0.0f;
-            if (e == hipSuccess && st == HX_OK) e = hipEventElapsedTime(&t, e0, e1);
             if (e != hipSuccess) st = hip_fail(e, "batch autotune timing");
+            if (st == HX_OK) elapsed(&t);
             ms.push_back(t);
+        }
+        // Throughput: 4 S calls round-robin over the S streams, bracketed
+        // by e0 (every stream waits for it) and e1 (after every stream).
+        std::vector<float> tp;
+        const int K = 4 * S;
+        for (int r = 0; r < 3 && st == HX_OK; ++r) {
+            e = hipEventRecord(e0, s);
+            for (int i = 1; i < S && e == hipSuccess; ++i) e = hipStreamWaitEvent(st_[i], e0, 0);
+            for (int k = 0; k < K && e == hipSuccess && st == HX_OK; ++k)
+                st = run_batched(p, imgs, n, nullptr, c.pass, c.ty, st_[k % S], k % S);
+            for (int i = 1; i < S && e == hipSuccess && st == HX_OK; ++i) {
+                e = hipEventRecord(done_[i], st_[i]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(s, done_[i], 0);
+            }
+            if (e == hipSuccess && st == HX_OK) e = hipEventRecord(e1, s);
+            float t = 0.0f;
+            if (e != hipSuccess && st == HX_OK) st = hip_fail(e, "batch autotune timing");
+            if (st == HX_OK) elapsed(&t);
+            tp.push_back(t / K);
         }
         if (st != HX_OK) break;
         std::sort(ms.begin(), ms.end());
-        const float med = ms[ms.size() / 2];
-        trials.push_back({c, med});
-        if (med < best_ms) {
-            best_ms = med;
+        std::sort(tp.begin(), tp.end());
+        const Trial t{c, ms[ms.size() / 2], tp[tp.size() / 2]};
+        logf(1, "batch tuner: %d-row tiles, pass %d: %.4f ms per call with %d in flight, "
+             "%.4f ms alone", c.ty, c.pass, t.tput_ms, S, t.ms);
+        trials.push_back(t);
+        if (t.tput_ms < best_ms) {
+            best_ms = t.tput_ms;
             best = c;
         }
     }
-    e = hipStreamSynchronize(s);
+    for (int i = 0; i < S; ++i) {
+        const hipError_t ei = hipStreamSynchronize(st_[i]);
+        if (e == hipSuccess) e = ei;
+    }
     cleanup();
     if (st != HX_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "batch autotune");
     if (best_ms >= 1e30f) return fail(HX_E_UNSUPPORTED, "no batch schedule could run");
     p->batch_tuned[key] = best;
+    logf(1, "batch tuner: class (2^%d px, 2^%d images) -> %d-row tiles, pass %d", key.px,
+         key.n, best.ty, best.pass);
     if (tile_h) *tile_h = best.ty;
     if (pass_mode) *pass_mode = best.pass;
     if (cache_path) {
@@ -293,12 +343,13 @@ hx_status hx_autotune_batch(hx_pipeline* p, const hx_image* imgs, int32_t n,
         for (const Trial& t : trials)
             std::fprintf(f,
                          "{\"batch_trial\": {\"ksize\": %d, \"px_log2\": %d, \"n_log2\": %d, "
-                         "\"tile_h\": %d, \"pass\": %d, \"ms\": %.5f, \"pixels\": %lld, "
-                         "\"images\": %d}}\n",
-                         p->prm.ksize, key.px, key.n, t.c.ty, t.c.pass, t.ms, (long long)total, n);
+                         "\"tile_h\": %d, \"pass\": %d, \"ms\": %.5f, \"tput_ms\": %.5f, "
+                         "\"in_flight\": %d, \"pixels\": %lld, \"images\": %d}}\n",
+                         p->prm.ksize, key.px, key.n, t.c.ty, t.c.pass, t.ms, t.tput_ms, S,
+                         (long long)total, n);
         std::fprintf(f,
                      "{\"batch\": {\"ksize\": %d, \"px_log2\": %d, \"n_log2\": %d, "
-                     "\"tile_h\": %d, \"pass\": %d, \"ms\": %.5f}}\n",
+                     "\"tile_h\": %d, \"pass\": %d, \"tput_ms\": %.5f}}\n",
                      p->prm.ksize, key.px, key.n, best.ty, best.pass, best_ms);
         std::fclose(f);
     }

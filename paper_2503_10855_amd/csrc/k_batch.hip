@@ -36,11 +36,20 @@ namespace hx {
 #ifndef HX_SWEEP_WAVES
 #define HX_SWEEP_WAVES 3
 #endif
+#ifndef HX_BATCH_WG_WAVES
+#define HX_BATCH_WG_WAVES 1
+#endif
 constexpr int kBC = HX_BATCH_C;    // columns per lane of the batch sweep
 constexpr int kBTY = HX_BATCH_TY;  // default rows per sweep tile
+// Waves per workgroup of the pass kernels.  One: a wave slot freed by a
+// finished tile takes the next item at once, where a 4-wave workgroup
+// waits for room for all four; with calls in flight on several streams
+// that lets one call's last partial round of tiles overlap the next call.
+constexpr int kWG = HX_BATCH_WG_WAVES;
 
 int batch_sweep_c() { return kBC; }
 int batch_sweep_ty() { return kBTY; }
+int batch_wg_waves() { return kWG; }
 
 __host__ __device__ inline int p2_rows(int64_t W) {
     const int64_t r = 4096 / (W > 0 ? W : 1);
@@ -90,7 +99,7 @@ __global__ void k_batch_reset(const uint8_t* __restrict__ table, uint32_t* slots
 
 // Index of this wave among all waves of the grid (XCD-contiguous).
 __device__ __forceinline__ int global_wave() {
-    return __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 +
+    return __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * kWG +
                                           (int)(threadIdx.x >> 6));
 }
 
@@ -100,11 +109,11 @@ __device__ __forceinline__ int global_wave() {
 // image also clears the image's max slot (pass 1 folds into it after this
 // kernel), so SPECULATE needs no reset kernel.
 template <int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
     using S = SweepShape<KS, kBC, SM_MAXONLY>;
     const TableView tv = view(table);
-    const int nw = gridDim.x * 4;
+    const int nw = gridDim.x * kWG;
     const uint64_t ep = (uint64_t)*as_global(tv.hdr.epoch) << 32;
     for (int k = global_wave(); k < tv.hdr.n_items0; k += nw) {
         const BatchItem it = tv.items0[k];
@@ -130,7 +139,7 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
                                                    : SM_MAXONLY;
     using S = SweepShape<KS, kBC, M1>;
     const TableView tv = view(table);
-    const int nw = gridDim.x * 4;
+    const int nw = gridDim.x * kWG;
     for (int k = global_wave(); k < tv.hdr.n_items1; k += nw) {
         const BatchItem it = tv.items1[k];
         const ImgArgs a = tv.imgs[it.image];
@@ -165,23 +174,23 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
 // registers): left alone, the scheduler keeps more rows in flight and
 // the kernels fall to two waves per SIMD, which measured slower.
 template <int KS, int PASS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p1(const uint8_t* __restrict__ table, Taps tp) {
     batch_p1_body<KS, PASS>(table, tp);
 }
 
 template <int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p1s(const uint8_t* __restrict__ table, Taps tp) {
     batch_p1_body<KS, HX_PASS_SPECULATE>(table, tp);
 }
 
 template <int KS, int PASS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
     using S = SweepShape<KS, kBC, SM_MASK>;
     const TableView tv = view(table);
-    const int nw = gridDim.x * 4;
+    const int nw = gridDim.x * kWG;
     const int lane = lane_id();
     for (int k = global_wave(); k < tv.hdr.n_items2; k += nw) {
         const BatchItem it = tv.items2[k];
@@ -306,7 +315,7 @@ hipError_t launch_batch_phase(int ks, int pass_mode, int phase, const void* d_ta
     const uint8_t* tab = (const uint8_t*)d_table;
     Taps tc = t;
     void* args[] = {(void*)&tab, (void*)&tc};
-    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * kWG), args, 0, s);
 }
 
 }  // namespace hx

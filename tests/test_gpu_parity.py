@@ -61,6 +61,7 @@ SCHEDULES = [
     (256, 16, 4, 1, 0), (256, 64, 4, 1, 0), (256, 128, 4, 1, 0),
     (64, 64, 4, 2, 0), (128, 16, 4, 2, 0), (256, 32, 4, 2, 0), (256, 64, 4, 2, 0),
     (256, 64, 4, 3, 0), (256, 32, 4, 3, 0), (256, 48, 4, 3, 0), (256, 96, 4, 3, 0),
+    (256, 16, 4, 3, 0), (256, 24, 4, 3, 0),
     (256, 160, 4, 3, 0),
     (64, 16, 1, 1, 1), (32, 32, 1, 1, 2),
 ]
