@@ -67,7 +67,7 @@ def source_hash(sources=None):
 def measured_traffic(kernel, pixels, path=TRAFFIC_FILE, sources=None, tile_h=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when absent, taken on different kernel sources, or
-    taken at another sweep tile height than `tile_h` (when both state one)."""
+    (for summaries taken per sweep tile height) not taken at `tile_h`."""
     try:
         with open(path) as f:
             t = json.load(f)
@@ -75,9 +75,11 @@ def measured_traffic(kernel, pixels, path=TRAFFIC_FILE, sources=None, tile_h=Non
         return None
     if t.get("source_hash") != source_hash(sources) or t.get("pixels") != pixels:
         return None
-    if tile_h is not None and t.get("tile_h") not in (None, tile_h):
-        return None
-    k = t.get("kernels", {}).get(kernel)
+    kernels = t.get("kernels", {})
+    if "by_tile_h" in t:
+        # Counters taken at several sweep tile heights: the one in use.
+        kernels = t["by_tile_h"].get(str(tile_h), {}).get("kernels", {})
+    k = kernels.get(kernel)
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -232,6 +234,9 @@ def main():
                          "to this many streams in turn, each with its own output buffers "
                          "(default 4; 1: one stream)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
+    ap.add_argument("--zero-copy", action="store_true",
+                    help="serve: requests go in through reserved pinned slots (the bench "
+                         "copies each crop into its slot) and masks are read in place")
     ap.add_argument("--srad-side", type=int, default=4096, help="srad: image side")
     ap.add_argument("--srad-iters", type=int, default=100, help="srad: iterations per step")
     ap.add_argument("--images-reduce", type=int, default=8,
@@ -485,7 +490,8 @@ def percentiles(v, qs=(50, 99)):
     return {f"p{q}": round(float(np.percentile(v, q)) * 1e3, 4) for q in qs}
 
 
-def serve_leg(hx, n, rate, budget_mb, streams, max_batch, pool_n=None, verbose=True):
+def serve_leg(hx, n, rate, budget_mb, streams, max_batch, pool_n=None, verbose=True,
+              zero_copy=False):
     """Continuous batching: n requests (crops of a pool of 4096x4096 images,
     sides log-uniform in [64, 4096]) arrive as a Poisson process at `rate`
     per second and are submitted at their scheduled times; latency runs from
@@ -534,18 +540,36 @@ def serve_leg(hx, n, rate, budget_mb, streams, max_batch, pool_n=None, verbose=T
             while done < n:
                 now = srv.now()
                 while i < n and t0 + arrivals[i] <= now:
-                    t = srv.try_submit(views[i], arrival=t0 + arrivals[i])
-                    if t is None:
-                        break  # pinned pool full until finished requests are polled
-                    pending[t] = (i, np.empty(views[i].shape, np.uint8))
+                    if zero_copy:
+                        # The caller writes the request into its pinned
+                        # slot (here: copies the crop) and commits it.
+                        rv = srv.reserve(views[i].shape)
+                        if rv is None:
+                            break
+                        t, slot = rv
+                        slot[...] = views[i]
+                        srv.commit(t, arrival=t0 + arrivals[i])
+                        pending[t] = (i, None)
+                    else:
+                        t = srv.try_submit(views[i], arrival=t0 + arrivals[i])
+                        if t is None:
+                            break  # pinned pool full until finished requests are polled
+                        pending[t] = (i, np.empty(views[i].shape, np.uint8))
                     i += 1
                 for t in list(pending):
                     k, buf = pending[t]
-                    r = srv.poll_timed(t, buf.shape, out=buf)
+                    if zero_copy:
+                        r = srv.view(t, views[k].shape)
+                        if r is not None and k % 500 == 0:
+                            outs[k] = r[0].copy()
+                        if r is not None:
+                            srv.release(t)
+                    else:
+                        r = srv.poll_timed(t, buf.shape, out=buf)
+                        if r is not None and k % 500 == 0:
+                            outs[k] = buf
                     if r is not None:
                         lat[k], svc[k] = r[1], r[2]
-                        if k % 500 == 0:
-                            outs[k] = buf
                         del pending[t]
                         done += 1
                 if now - t0 > next_report:
@@ -586,6 +610,7 @@ def serve_leg(hx, n, rate, budget_mb, streams, max_batch, pool_n=None, verbose=T
         "pipeline_scratch_mib": round(own / 2**20, 1),
         "sample_masks_identical_to_per_image": same,
         "sample": len(outs),
+        "submission": "reserve/commit, view/release" if zero_copy else "submit/poll",
     }
 
 
@@ -593,7 +618,7 @@ def run_serve(args, hx):
     """The serving workload alone: its line carries throughput and the
     latency percentiles."""
     r = serve_leg(hx, args.requests, args.rate, args.budget_mb, args.streams,
-                  args.max_batch)
+                  args.max_batch, zero_copy=args.zero_copy)
     line = {
         "metric": METRIC,
         "value": r["mpx_s"],
@@ -605,7 +630,7 @@ def run_serve(args, hx):
         "config": {"workload": r["workload"], "requests": r["requests"],
                    "rate_per_s": r["rate_per_s"], "pixels": r["pixels"],
                    "budget_mib": r["budget_mib"], "streams": r["streams"],
-                   "max_batch": r["max_batch"]},
+                   "max_batch": r["max_batch"], "submission": r["submission"]},
     }
     line.update({k: v for k, v in r.items() if k not in ("workload", "mpx_s", "requests",
                                                           "rate_per_s", "pixels",

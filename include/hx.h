@@ -308,9 +308,9 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
  * pipeline holds HX_FORM_BATCH_STORE, STORE -- and keeps the one with the
  * highest throughput for the batch's class (floor(log2) of its total
  * pixels and of n): the time per call with min(batch_contexts, 4) calls in
- * flight on as many streams of the tuner's own (median of three runs of 4
- * calls per stream; the time of one call alone, median of five, is
- * recorded beside it).  Later batched calls of that class use the choice
+ * flight on as many streams of the tuner's own (median of three runs of
+ * 12 calls per stream, after about 30 ms of warm-up calls; the time of
+ * one call alone, median of five, is recorded beside it).  Later batched calls of that class use the choice
  * unless the pass structure is fixed or a schedule forced.  The calls in
  * flight all write the caller's masks, with the same bits, so on return
  * they hold the batch's result.  Blocking.  Appends one
@@ -395,6 +395,31 @@ hx_status hx_serve_poll(hx_server* s, uint64_t ticket, uint8_t* h_mask,
 hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
                               int64_t mask_pitch, double* latency_s,
                               double* service_s);
+
+/* Zero-copy submission, for callers that produce the request image
+ * themselves (a decoder, a camera ring): hx_serve_reserve takes room for
+ * an h x w request in the server's pinned pool and returns it in *h_slot
+ * (h rows of w fp32 values, row pitch w, 256-byte aligned); the caller
+ * writes the image there and queues it with hx_serve_commit (arrival_s as
+ * for submit), which copies nothing.  The slot is the caller's between the
+ * two calls; hx_serve_cancel gives an uncommitted slot back.  Errors as for
+ * submit (HX_E_PENDING: pool full, HX_E_BUSY: never fits); commit and
+ * cancel return HX_E_NOT_FOUND for an unknown ticket and HX_E_INVALID for
+ * one that is not a reserved slot. */
+hx_status hx_serve_reserve(hx_server* s, int64_t h, int64_t w, float** h_slot,
+                           uint64_t* ticket);
+hx_status hx_serve_commit(hx_server* s, uint64_t ticket, double arrival_s);
+hx_status hx_serve_cancel(hx_server* s, uint64_t ticket);
+
+/* Zero-copy collection: once a request is done, *h_mask points at its mask
+ * in the pinned pool (h rows of w bytes, row pitch w) and the latency and
+ * service time are returned as by poll_timed (nullable); the mask stays
+ * there, and the pool room held, until hx_serve_release.  HX_E_PENDING
+ * while not done; errors otherwise as for poll.  (hx_serve_poll copies the
+ * mask out and releases in one call.) */
+hx_status hx_serve_view(hx_server* s, uint64_t ticket, const uint8_t** h_mask,
+                        double* latency_s, double* service_s);
+hx_status hx_serve_release(hx_server* s, uint64_t ticket);
 
 /* Seconds on the server's monotonic clock. */
 double hx_serve_now(const hx_server* s);

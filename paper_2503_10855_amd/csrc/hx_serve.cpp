@@ -4,7 +4,9 @@
 // (the AsyncCall attribute) and allocates all memory up front from dynamic
 // constants (Global Code Motion; The Host Rust Interface).  Here that
 // becomes a serving loop:
-//   submit   copies the request image into a pinned host pool and queues it;
+//   submit   copies the request image into a pinned host pool and queues it
+//            (or: reserve hands the caller a slot of that pool to write
+//            the image into, commit queues it);
 //   admit    a scheduler thread moves queued requests, oldest first, into
 //            the device arena while their buffers fit the HBM budget;
 //   launch   every admitted request not yet launched joins the next batch
@@ -14,7 +16,8 @@
 //   retire   a host callback at the end of the batch stamps completion;
 //            the scheduler releases the device buffers;
 //   poll     hands the mask and the latency (completion minus the
-//            request's scheduled arrival) to the caller.
+//            request's scheduled arrival) to the caller (or: view lends
+//            the mask where it lies in the pool until release).
 // Requests that arrive while others are on the device are admitted as
 // memory frees up and launched in the next batch.  Batches run the
 // pipeline's batched form (SPECULATE); its scratch -- batch contexts with
@@ -213,7 +216,9 @@ class RangeAlloc {
     std::map<size_t, size_t> free_;
 };
 
-enum ReqState { QUEUED, ADMITTED, LAUNCHED, DONE };
+// RESERVED: a slot handed to the caller (hx_serve_reserve) not yet
+// committed; the scheduler never sees it.
+enum ReqState { RESERVED, QUEUED, ADMITTED, LAUNCHED, DONE };
 
 struct Request {
     uint64_t id;
@@ -400,6 +405,75 @@ void scheduler(hx_server* s) {
 }  // namespace
 }  // namespace hx
 
+namespace hx {
+namespace {
+
+// A new request of h x w with room in the pinned pool, in state RESERVED
+// (invisible to the scheduler).  Called with s->mu held.
+hx_status new_request(hx_server* s, int64_t h, int64_t w, Request** out) {
+    if (h < 1 || w < 1) return fail(HX_E_INVALID, "bad image shape");
+    if (h * w > s->p->prm.max_pixels)
+        return fail(HX_E_INVALID, "request of %lld pixels exceeds max_pixels",
+                    (long long)(h * w));
+    auto r = std::make_unique<Request>();
+    r->h = h;
+    r->w = w;
+    r->state = RESERVED;
+    r->host_bytes = align_up(r->in_bytes()) + align_up(r->mask_bytes());
+    const size_t dev_need = r->host_bytes;
+    if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
+    if (dev_need > s->dev_alloc->size() || r->host_bytes > s->host_alloc->size())
+        return fail(HX_E_BUSY, "request of %zu bytes can never fit the budget", dev_need);
+    if (s->stop) return fail(HX_E_INVALID, "server is shutting down");
+    // Never wait here for pool room: it is freed only by collecting
+    // finished requests, which a single-threaded caller could then never do.
+    if (!s->host_alloc->alloc(r->host_bytes, &r->host_off))
+        return fail(HX_E_PENDING, "pinned pool full: poll finished requests, then retry");
+    r->id = s->next_id++;
+    *out = r.get();
+    s->reqs.emplace(r->id, std::move(r));
+    return HX_OK;
+}
+
+// Queue a filled request.  Called with s->mu held.
+void queue_request(hx_server* s, Request* r, double arrival_s) {
+    r->arrival = arrival_s;
+    r->state = QUEUED;
+    s->queued.push_back(r);
+    s->cv.notify_all();
+}
+
+// The request of `ticket` in state `want`, or an error.  Called with
+// s->mu held.
+hx_status find_request(hx_server* s, uint64_t ticket, ReqState want, Request** out) {
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return fail(HX_E_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    if (r->state != want) {
+        if (want == DONE) {
+            if (s->sticky != HX_OK)
+                return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
+            if (r->state != RESERVED) return HX_E_PENDING;
+        }
+        return fail(HX_E_INVALID, "ticket %llu is not %s", (unsigned long long)ticket,
+                    want == DONE ? "a committed request" : "a reserved slot");
+    }
+    if (want == DONE && s->sticky != HX_OK)
+        return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
+    *out = r;
+    return HX_OK;
+}
+
+// Give a request's pool room back and forget it.  Called with s->mu held.
+void drop_request(hx_server* s, Request* r) {
+    s->host_alloc->release(r->host_off, r->host_bytes);
+    s->reqs.erase(r->id);
+}
+
+}  // namespace
+}  // namespace hx
+
 using namespace hx;
 
 extern "C" {
@@ -471,39 +545,80 @@ hx_status hx_serve_create(hx_pipeline* p, const hx_serve_params* sp, void* d_are
 
 double hx_serve_now(const hx_server* s) { return s ? now_s(s) : 0.0; }
 
+
 hx_status hx_serve_submit(hx_server* s, const float* h_src, int64_t h, int64_t w,
                           int64_t pitch, double arrival_s, uint64_t* ticket) {
     if (!s || !h_src || !ticket) return fail(HX_E_INVALID, "NULL argument");
-    if (h < 1 || w < 1 || pitch < w) return fail(HX_E_INVALID, "bad image shape or pitch");
-    if (h * w > s->p->prm.max_pixels)
-        return fail(HX_E_INVALID, "request of %lld pixels exceeds max_pixels",
-                    (long long)(h * w));
-    auto r = std::make_unique<Request>();
-    r->h = h;
-    r->w = w;
-    r->arrival = arrival_s;
-    r->host_bytes = align_up(r->in_bytes()) + align_up(r->mask_bytes());
-    const size_t dev_need = r->host_bytes;
+    if (pitch < w) return fail(HX_E_INVALID, "bad image shape or pitch");
     std::unique_lock<std::mutex> lk(s->mu);
-    if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
-    if (dev_need > s->dev_alloc->size() || r->host_bytes > s->host_alloc->size())
-        return fail(HX_E_BUSY, "request of %zu bytes can never fit the budget", dev_need);
-    if (s->stop) return fail(HX_E_INVALID, "server is shutting down");
-    // Never wait here for pool room: it is freed only by hx_serve_poll,
-    // which a single-threaded caller could then never reach.
-    if (!s->host_alloc->alloc(r->host_bytes, &r->host_off))
-        return fail(HX_E_PENDING, "pinned pool full: poll finished requests, then retry");
-    r->id = s->next_id++;
-    Request* rp = r.get();
-    s->reqs.emplace(rp->id, std::move(r));
+    Request* rp = nullptr;
+    hx_status st = new_request(s, h, w, &rp);
+    if (st != HX_OK) return st;
     lk.unlock();
     // Copy the rows into the pinned pool (the caller may reuse h_src).
+    // The request is RESERVED meanwhile: nothing else touches its room.
     s->copies->copy(s->host + rp->host_off, sizeof(float) * (size_t)w, h_src,
                     sizeof(float) * (size_t)pitch, sizeof(float) * (size_t)w, h);
     lk.lock();
-    s->queued.push_back(rp);
+    queue_request(s, rp, arrival_s);
     *ticket = rp->id;
-    s->cv.notify_all();
+    return HX_OK;
+}
+
+hx_status hx_serve_reserve(hx_server* s, int64_t h, int64_t w, float** h_slot,
+                           uint64_t* ticket) {
+    if (!s || !h_slot || !ticket) return fail(HX_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* rp = nullptr;
+    hx_status st = new_request(s, h, w, &rp);
+    if (st != HX_OK) return st;
+    *h_slot = reinterpret_cast<float*>(s->host + rp->host_off);
+    *ticket = rp->id;
+    return HX_OK;
+}
+
+hx_status hx_serve_commit(hx_server* s, uint64_t ticket, double arrival_s) {
+    if (!s) return fail(HX_E_INVALID, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = nullptr;
+    hx_status st = find_request(s, ticket, RESERVED, &r);
+    if (st != HX_OK) return st;
+    if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
+    if (s->stop) return fail(HX_E_INVALID, "server is shutting down");
+    queue_request(s, r, arrival_s);
+    return HX_OK;
+}
+
+hx_status hx_serve_cancel(hx_server* s, uint64_t ticket) {
+    if (!s) return fail(HX_E_INVALID, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = nullptr;
+    hx_status st = find_request(s, ticket, RESERVED, &r);
+    if (st != HX_OK) return st;
+    drop_request(s, r);
+    return HX_OK;
+}
+
+hx_status hx_serve_view(hx_server* s, uint64_t ticket, const uint8_t** h_mask,
+                        double* latency_s, double* service_s) {
+    if (!s || !h_mask) return fail(HX_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = nullptr;
+    hx_status st = find_request(s, ticket, DONE, &r);
+    if (st != HX_OK) return st;
+    *h_mask = s->host + r->host_off + align_up(r->in_bytes());
+    if (latency_s) *latency_s = r->done_t - r->arrival;
+    if (service_s) *service_s = r->done_t - r->launch_t;
+    return HX_OK;
+}
+
+hx_status hx_serve_release(hx_server* s, uint64_t ticket) {
+    if (!s) return fail(HX_E_INVALID, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = nullptr;
+    hx_status st = find_request(s, ticket, DONE, &r);
+    if (st != HX_OK) return st;
+    drop_request(s, r);
     return HX_OK;
 }
 
@@ -516,15 +631,9 @@ hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
                               int64_t mask_pitch, double* latency_s, double* service_s) {
     if (!s) return fail(HX_E_INVALID, "NULL server");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return fail(HX_E_NOT_FOUND, "unknown ticket %llu",
-                                         (unsigned long long)ticket);
-    Request* r = it->second.get();
-    if (r->state != DONE) {
-        if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
-        return HX_E_PENDING;
-    }
-    if (s->sticky != HX_OK) return fail(s->sticky, "server failed: %s", s->sticky_msg.c_str());
+    Request* r = nullptr;
+    hx_status st = find_request(s, ticket, DONE, &r);
+    if (st != HX_OK) return st;
     if (h_mask) {
         if (mask_pitch < r->w) return fail(HX_E_INVALID, "mask_pitch below width");
         s->copies->copy(h_mask, (size_t)mask_pitch,
@@ -533,8 +642,7 @@ hx_status hx_serve_poll_timed(hx_server* s, uint64_t ticket, uint8_t* h_mask,
     }
     if (latency_s) *latency_s = r->done_t - r->arrival;
     if (service_s) *service_s = r->done_t - r->launch_t;
-    s->host_alloc->release(r->host_off, r->host_bytes);
-    s->reqs.erase(it);
+    drop_request(s, r);
     return HX_OK;
 }
 

@@ -90,6 +90,14 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
     "hx_serve_now": (ctypes.c_double, [_P]),
+    "hx_serve_reserve": (ctypes.c_int, [_P, _i64, _i64, ctypes.POINTER(_P),
+                                        ctypes.POINTER(_u64)]),
+    "hx_serve_commit": (ctypes.c_int, [_P, _u64, ctypes.c_double]),
+    "hx_serve_cancel": (ctypes.c_int, [_P, _u64]),
+    "hx_serve_view": (ctypes.c_int, [_P, _u64, ctypes.POINTER(_P),
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "hx_serve_release": (ctypes.c_int, [_P, _u64]),
     "hx_srad": (ctypes.c_int, [_P, _P, _i64, _i64, _i64, _i32, ctypes.c_float, _i32, _P,
                                _P]),
     "hx_schedule_compile": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Schedule)]),
@@ -423,6 +431,51 @@ class Server:
             return None
         _check(st, "hx_serve_poll_timed")
         return m, lat.value, svc.value
+
+    def reserve(self, shape):
+        """Zero-copy submission: (ticket, slot), slot a float32 numpy array
+        of `shape` over the server's pinned pool, to be filled by the
+        caller and then queued with commit(ticket); None while the pool is
+        full."""
+        import numpy as np
+        h, w = shape
+        ptr, t = _P(), _u64()
+        st = _lib.hx_serve_reserve(self._h, h, w, ctypes.byref(ptr), ctypes.byref(t))
+        if st == HX_E_PENDING:
+            return None
+        _check(st, "hx_serve_reserve")
+        buf = (ctypes.c_float * (h * w)).from_address(ptr.value)
+        return t.value, np.ctypeslib.as_array(buf).reshape(h, w)
+
+    def commit(self, ticket, arrival=None):
+        """Queue a reserved slot (the slot must not be written afterwards)."""
+        _check(_lib.hx_serve_commit(self._h, ticket,
+                                    self.now() if arrival is None else arrival),
+               "hx_serve_commit")
+
+    def cancel(self, ticket):
+        _check(_lib.hx_serve_cancel(self._h, ticket), "hx_serve_cancel")
+
+    def view(self, ticket, shape):
+        """Zero-copy collection: (mask, latency_s, service_s) with mask a
+        read-only uint8 numpy view of the pinned pool, valid until
+        release(ticket); None while pending."""
+        import numpy as np
+        h, w = shape
+        ptr = _P()
+        lat, svc = ctypes.c_double(), ctypes.c_double()
+        st = _lib.hx_serve_view(self._h, ticket, ctypes.byref(ptr), ctypes.byref(lat),
+                                ctypes.byref(svc))
+        if st == HX_E_PENDING:
+            return None
+        _check(st, "hx_serve_view")
+        buf = (ctypes.c_uint8 * (h * w)).from_address(ptr.value)
+        m = np.ctypeslib.as_array(buf).reshape(h, w)
+        m.flags.writeable = False
+        return m, lat.value, svc.value
+
+    def release(self, ticket):
+        _check(_lib.hx_serve_release(self._h, ticket), "hx_serve_release")
 
     def stats(self):
         v = [_u64() for _ in range(4)]

@@ -138,3 +138,57 @@ def test_serve_submit_never_blocks(hx):
     assert np.array_equal(last[0], ref)
     for (m, _), r in zip(res, refs):
         assert np.array_equal(m, r)
+
+
+def test_serve_zero_copy_slots(hx):
+    """Reserve / commit / view / release: the caller writes each request into
+    its pinned slot and reads the mask where it lies; the masks equal the
+    per-image ones.  A cancelled slot gives its room back, and tickets in
+    the wrong state are refused."""
+    sizes = [(300, 500), (1080, 1920), (64, 64), (517, 259), (1, 300)]
+    imgs = [synth.image(h, w, 83, i) for i, (h, w) in enumerate(sizes)]
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 23, max_images=8, forms=hx.FORM_BATCH,
+                     batch_contexts=2) as p:
+        own = p.memory()[0]
+        with hx.Server(p, hbm_budget=own + (256 << 20), streams=2, max_batch=4) as srv:
+            print("serve: zero-copy slots", flush=True)
+            t0, slot0 = srv.reserve((2048, 2048))
+            srv.cancel(t0)
+            with pytest.raises(hx.HxError) as ei:
+                srv.commit(t0)
+            assert ei.value.status == hx.HX_E_NOT_FOUND
+            tickets = []
+            for a in imgs:
+                t, slot = srv.reserve(a.shape)
+                assert slot.shape == a.shape and slot.dtype == np.float32
+                slot[...] = a
+                tickets.append(t)
+            with pytest.raises(hx.HxError) as ei:
+                srv.view(tickets[0], sizes[0])
+            assert ei.value.status == hx.HX_E_INVALID
+            for t in tickets:
+                srv.commit(t)
+            with pytest.raises(hx.HxError) as ei:
+                srv.commit(tickets[0])
+            assert ei.value.status == hx.HX_E_INVALID
+            got = {}
+            deadline = time.time() + 60
+            while len(got) < len(tickets) and time.time() < deadline:
+                for t, shp in zip(tickets, sizes):
+                    if t in got:
+                        continue
+                    r = srv.view(t, shp)
+                    if r is not None:
+                        m, lat, svc = r
+                        assert not m.flags.writeable and lat >= svc >= 0
+                        got[t] = m.copy()
+                        srv.release(t)
+                time.sleep(1e-4)
+            assert len(got) == len(tickets)
+            with pytest.raises(hx.HxError) as ei:
+                srv.release(tickets[0])
+            assert ei.value.status == hx.HX_E_NOT_FOUND
+    with hx.Pipeline(theta=THETA, max_pixels=1 << 23, max_images=8) as q:
+        refs = [q.edge_detect(torch.from_numpy(a).cuda()).cpu().numpy() for a in imgs]
+    for t, ref in zip(tickets, refs):
+        assert np.array_equal(got[t], ref)
