@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="serve: compute streams (default 4); batch: consecutive batches go "
                          "to this many streams in turn, each with its own output buffers "
-                         "(default 4; 1: one stream)")
+                         "(default 6; 1: one stream)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
     ap.add_argument("--zero-copy", action="store_true",
                     help="serve: requests go in through reserved pinned slots (the bench "
@@ -266,7 +266,7 @@ def main():
     if args.warmup is None:
         args.warmup = 20 if args.mode == "batch" else 5
     if args.streams is None:
-        args.streams = 4
+        args.streams = 6 if args.mode in ("batch", "tune-batch") else 4
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); "
@@ -307,9 +307,11 @@ def main():
     pixels = wl.pixels
     sync = torch.cuda.synchronize
 
+    # One batch context per stream (at least the library's default 4), so
+    # that each stream's output set keeps its own table and graph.
     with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=wl.theta,
                      max_pixels=pixels, max_images=max(len(srcs), 1),
-                     pass_mode=args.pass_mode) as p:
+                     pass_mode=args.pass_mode, batch_contexts=min(8, max(4, S))) as p:
         sched = p.schedule(*wl.sizes[0])
         # The batched launch's tile height and pass structure, chosen by the
         # batch autotuner on this batch (unless a pass structure is fixed).
@@ -815,7 +817,8 @@ def run_tune_batch(args, hx):
     with tempfile.TemporaryDirectory() as td:
         cache = os.path.join(td, "tune_batch.jsonl")
         with hx.Pipeline(ksize=wl.ksize, sigma=wl.sigma, theta=wl.theta,
-                         max_pixels=wl.pixels, max_images=len(srcs)) as p:
+                         max_pixels=wl.pixels, max_images=len(srcs),
+                         batch_contexts=min(8, max(1, args.streams))) as p:
             print(f"tune-batch: {wl.name}", file=sys.stderr, flush=True)
             th, pm = p.autotune_batch(srcs, cache_path=cache)
         lines = [json.loads(x) for x in open(cache)]

@@ -307,8 +307,8 @@ hx_status hx_autotune(hx_pipeline* p, int64_t height, int64_t width,
  * 16..160 rows x pass structures SPECULATE, RECOMPUTE and, when the
  * pipeline holds HX_FORM_BATCH_STORE, STORE -- and keeps the one with the
  * highest throughput for the batch's class (floor(log2) of its total
- * pixels and of n): the time per call with min(batch_contexts, 4) calls in
- * flight on as many streams of the tuner's own (median of three runs of
+ * pixels and of n): the time per call with batch_contexts calls in flight
+ * on as many streams of the tuner's own (median of three runs of
  * 12 calls per stream, after about 30 ms of warm-up calls; the time of
  * one call alone, median of five, is recorded beside it).  Later batched calls of that class use the choice
  * unless the pass structure is fixed or a schedule forced.  The calls in

@@ -233,13 +233,13 @@ hx_status hx_autotune_batch(hx_pipeline* p, const hx_image* imgs, int32_t n,
     if (total > p->prm.max_pixels) return fail(HX_E_INVALID, "batch exceeds max_pixels");
     TraceRange trace("hx.autotune_batch");
     DeviceGuard g(p->device);
-    // One stream per batch context (at most 4), call k on stream and
-    // context k mod S: the throughput trials keep that many calls in
-    // flight, as a caller feeding batches on several streams does.  All calls write the same masks with the same bits;
+    // One stream per batch context, call k on stream and context k mod S:
+    // the throughput trials keep that many calls in flight, as a caller
+    // feeding batches on as many streams does.  All calls write the same masks with the same bits;
     // after the last one the masks hold the result of any of them.
-    const int S = std::max(1, std::min(p->n_ctx, 4));
-    hipStream_t st_[4] = {};
-    hipEvent_t done_[4] = {};
+    const int S = std::max(1, std::min(p->n_ctx, hx_pipeline::kMaxContexts));
+    hipStream_t st_[hx_pipeline::kMaxContexts] = {};
+    hipEvent_t done_[hx_pipeline::kMaxContexts] = {};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);

@@ -624,6 +624,10 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                                            float& gmax, SpecTile* sp = nullptr) {
     using S = SweepShape<KS, C, MODE>;
     const int xs = x0 - S::HL;
+    // A tile that reaches the image's bottom runs only the rows the image
+    // still has, rounded up to the row step (its output rows are the same;
+    // a full-height sweep would compute up to ty - 8 rows of clamped rows).
+    ty = min(ty, (a.H - y0 + kSweepRowStep - 1) / kSweepRowStep * kSweepRowStep);
     // Vector rows: input rows that start on 4C-byte boundaries and, for the
     // mask-writing modes, mask rows that start on 4-byte boundaries.
     const bool vec_ok =
