@@ -21,6 +21,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# HIP gives a process 4 hardware queues unless told otherwise, and torch's
+# own stream takes one: the batches bench.py keeps in flight on several
+# streams then share queues and stop overlapping.  Ask for 8 (read when
+# HIP initialises, which happens after this point).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 METRIC = ("Mpixel/s and %HBM-roofline, batched vs per-image; "
           "p50/p99 latency at QPS")
 HBM_PEAK_GBS = 8000.0
@@ -232,7 +239,7 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="serve: compute streams (default 4); batch: consecutive batches go "
                          "to this many streams in turn, each with its own output buffers "
-                         "(default 6; 1: one stream)")
+                         "(default 4; 1: one stream)")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: images per batch")
     ap.add_argument("--zero-copy", action="store_true",
                     help="serve: requests go in through reserved pinned slots (the bench "
@@ -266,7 +273,7 @@ def main():
     if args.warmup is None:
         args.warmup = 20 if args.mode == "batch" else 5
     if args.streams is None:
-        args.streams = 6 if args.mode in ("batch", "tune-batch") else 4
+        args.streams = 4
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); "
