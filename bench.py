@@ -529,9 +529,18 @@ def serve_leg(hx, n, rate, budget_mb, streams, max_batch, pool_n=None, verbose=T
         arena = torch.empty(max(budget - own, 1 << 12), dtype=torch.uint8, device="cuda")
         with hx.Server(p, hbm_budget=budget, streams=streams,
                        max_batch=max_batch, arena=arena) as srv:
-            # Warm-up: every batch context captures its graph once.
-            warm = [srv.submit(views[i]) for i in range(min(64, n))]
-            for t, i in zip(warm, range(64)):
+            # Warm-up: every batch context captures its graph once.  A
+            # full pinned pool is drained before the next submission.
+            warm = []
+            for i in range(min(64, n)):
+                t = srv.try_submit(views[i])
+                while t is None:
+                    j, tj = warm.pop(0)
+                    while srv.poll(tj, views[j].shape) is None:
+                        time.sleep(1e-4)
+                    t = srv.try_submit(views[i])
+                warm.append((i, t))
+            for i, t in warm:
                 while srv.poll(t, views[i].shape) is None:
                     time.sleep(1e-4)
             st0 = srv.stats()

@@ -102,7 +102,7 @@ enum { HX_REDUCE_TREE = 0, HX_REDUCE_TWO_LEVEL = 1, HX_REDUCE_SEQUENTIAL = 2 };
  *  fusion_depth 4: all stencil stages in one pass (see pass_mode).
  *  For depth 2..4 the first kernel is a register sweep: each wave64 owns a
  *  strip of tile_w input columns (64, 128 or 256: 1, 2 or 4 per lane) and
- *  walks tile_h rows (16, 32, 64 or 128) down it. */
+ *  walks tile_h rows (a multiple of 8 in 8..256) down it. */
 typedef struct {
     int32_t tile_w, tile_h, fusion_depth, pass_mode, reduce_mode;
 } hx_schedule;

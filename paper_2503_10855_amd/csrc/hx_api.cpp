@@ -142,7 +142,9 @@ hx_status validate_schedule(const hx_pipeline* p, const hx_schedule& s) {
                     p->prm.ksize);
     if (!(s.tile_w == 64 || s.tile_w == 128 || s.tile_w == 256) ||
         !sweep_supported(p->prm.ksize, s.tile_w / 64, s.tile_h))
-        return fail(HX_E_INVALID, "sweep tile %dx%d not in {64,128,256}x{16,32,64,128}",
+        return fail(HX_E_INVALID,
+                    "sweep tile %dx%d: width not 64, 128 or 256, or height not a multiple "
+                    "of 8 in 8..256",
                     s.tile_w, s.tile_h);
     if (s.fusion_depth == 4 && s.pass_mode != HX_PASS_STORE &&
         s.pass_mode != HX_PASS_RECOMPUTE && s.pass_mode != HX_PASS_SPECULATE)
@@ -162,13 +164,14 @@ hx_schedule choose_schedule(const hx_pipeline* p, int64_t H, int64_t W) {
         s = it->second;
     } else if (fused_ks(p->prm.ksize)) {
         // Untuned: 256-column tiles, one wave each, and the tallest tile of
-        // 64, 32 or 16 rows that still gives every SIMD a wave (taller
+        // 64, 32, 16 or 8 rows that still gives every SIMD a wave (taller
         // tiles re-read fewer halo rows; a 1080p image in 64-row tiles
-        // would leave seven SIMDs in eight idle).
+        // would leave seven SIMDs in eight idle, and its 8-row tiles
+        // finish a call 5 % sooner than 16-row ones).
         const int64_t simds = 4 * (int64_t)(p->cu_count > 0 ? p->cu_count : 256);
         const int64_t strips = (W + 239) / 240;
         int th = 64;
-        while (th > 16 && strips * ((H + th - 1) / th) < simds) th /= 2;
+        while (th > 8 && strips * ((H + th - 1) / th) < simds) th /= 2;
         s = hx_schedule{256, th, 4, HX_PASS_STORE, HX_REDUCE_TREE};
     } else {
         s = hx_schedule{64, 16, 1, HX_PASS_STORE, HX_REDUCE_TREE};
@@ -245,22 +248,34 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
                     "hold %lld (raise max_pixels)",
                     (long long)img->height, (long long)img->width,
                     (long long)plane_need(img->height, img->width), (long long)p->plane_elems);
-    uint32_t* slot = (uint32_t*)p->slot1.ptr;
+    // The max slot: this call's of the pair, the other left at zero for the
+    // next call.  The fused STORE form's threshold kernel zeroes the other
+    // slot, so when the previous call left this one at zero the form needs
+    // no clearing launch; every other form clears both slots first.
+    uint32_t* const slots = (uint32_t*)p->slot1.ptr;
+    uint32_t* const slot = slots + p->img_parity;
+    uint32_t* const next = slots + (p->img_parity ^ 1);
+    p->img_parity ^= 1;
+    p->img_last_slot = slot;
+    const bool store_fused = s.fusion_depth == 4 && s.pass_mode == HX_PASS_STORE;
+    const bool slot_zero = p->img_next_zero;
+    p->img_next_zero = false;  // until this call's launches are all enqueued
     ImgArgs a = base_args(img, slot, d_max);
     const float theta = p->prm.thresh_frac;
     const int ks = p->prm.ksize;
-    HX_TRY(launch_fill_u32(slot, 0u, 1, stream));
+    if (!(store_fused && slot_zero)) HX_TRY(launch_fill_u32(slots, 0u, 2, stream));
     if (s.fusion_depth == 4) {
         const int c = s.tile_w / 64;
         if (s.pass_mode == HX_PASS_STORE) {
             a.fout = (float*)p->planeA.ptr;
             HX_TRY(launch_sweep(SM_STORE, ks, c, s.tile_h, a, p->taps, theta, stream));
-            HX_TRY(launch_threshold_code(a, theta, stream));
+            HX_TRY(launch_threshold_code(a, theta, stream, next));
         } else {
             HX_TRY(launch_sweep(SM_MAXONLY, ks, c, s.tile_h, a, p->taps, theta, stream));
             HX_TRY(launch_sweep(SM_MASK, ks, c, s.tile_h, a, p->taps, theta, stream));
             if (d_max) HX_TRY(launch_write_max(a, stream));
         }
+        p->img_next_zero = true;
         return HX_OK;
     }
     StageBufs b{};
@@ -283,6 +298,7 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
             HX_TRY(launch_zero_cross(a, b, b.L, tw1, th1, stream));
         }
         HX_TRY(launch_threshold_zg(a, b, theta, tw1, th1, stream));
+        p->img_next_zero = true;
         return HX_OK;
     }
     // Depth 1: one kernel per stage.
@@ -291,6 +307,7 @@ hx_status run_image(hx_pipeline* p, const hx_image* img, float* d_max,
     HX_TRY(launch_zero_cross(a, b, b.L, s.tile_w, s.tile_h, stream));
     HX_TRY(launch_sobel_max(a, b, s.tile_w, s.tile_h, s.reduce_mode, stream));
     HX_TRY(launch_threshold_zg(a, b, theta, s.tile_w, s.tile_h, stream));
+    p->img_next_zero = true;
     return HX_OK;
 }
 
@@ -1070,7 +1087,7 @@ hx_status hx_edge_detect_stages(hx_pipeline* p, const hx_image* img, float* d_B,
     if (st != HX_OK) return st;
     st = run_image(p, img, d_max, s, stream);
     if (st == HX_OK) {
-        ImgArgs a = base_args(img, (uint32_t*)p->slot1.ptr, d_max);
+        ImgArgs a = base_args(img, p->img_last_slot, d_max);
         StageBufs b{};
         b.op = a.op;
         b.B = (float*)p->planeA.ptr;

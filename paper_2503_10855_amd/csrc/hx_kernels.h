@@ -75,7 +75,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sweep(int mode, int ks, int c, int ty, const ImgArgs& a,
                         const Taps& t, float theta, hipStream_t s);
 // Pass 2 of STORE: code -> mask, and M into dmax.
-hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s);
+// zero_next (nullable): a word the kernel sets to 0 (the slot of the next
+// per-image call, which no wave of this kernel reads).
+hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s,
+                                 uint32_t* zero_next = nullptr);
 // Write M into a.dmax from a.slot (one thread).
 hipError_t launch_write_max(const ImgArgs& a, hipStream_t s);
 

@@ -155,6 +155,12 @@ struct hx_pipeline {
     hipEvent_t img_ev = nullptr;
     hipStream_t img_stream = nullptr;
     bool img_used = false;
+    // The per-image max slots: slot1 holds two; each call uses one and
+    // leaves the other at zero for the next call (img_next_zero says the
+    // previous call did).  img_last_slot: the slot of the last call.
+    int img_parity = 0;
+    bool img_next_zero = false;
+    uint32_t* img_last_slot = nullptr;
 
     // Batched launches.
     static constexpr int kMaxContexts = 8;

@@ -58,7 +58,7 @@ std::vector<hx_schedule> candidates(int ks) {
                                "fork-fuse(blur, sobel, laplacian, zero_cross); "};
         for (int depth = 2; depth <= 4; ++depth)
             for (int tw : {64, 128, 256})
-                for (int th : {16, 32, 64, 128}) {
+                for (int th : {8, 16, 32, 64, 128}) {
                     std::snprintf(b, sizeof b, "fork-tile[%d, %d](blur); ", th, tw);
                     const std::string t =
                         std::string(fuse[depth - 2]) + b + "warp-reduce(max_gradient);";

@@ -234,10 +234,14 @@ __global__ __launch_bounds__(256) void k_threshold_zg(ImgArgs a, StageBufs b,
 }
 
 // Pass 2 of STORE on one image: code -> mask, 4 pixels per thread.
-__global__ __launch_bounds__(256) void k_threshold_code(ImgArgs a, float theta) {
+__global__ __launch_bounds__(256) void k_threshold_code(ImgArgs a, float theta,
+                                                        uint32_t* zero_next) {
     const uint32_t m2 = *a.slot;
     const float thr2 = thr2_from(m2, theta);
-    if (a.dmax && blockIdx.x == 0 && threadIdx.x == 0) *a.dmax = max_from(m2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (a.dmax) *a.dmax = max_from(m2);
+        if (zero_next) *zero_next = 0u;  // the next per-image call's max slot
+    }
     const int wq = (a.W + 3) / 4;
     const bool mvec = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
     const int64_t total = (int64_t)wq * a.H;
@@ -367,10 +371,11 @@ hipError_t launch_threshold_zg(const ImgArgs& a, const StageBufs& b,
     return hipGetLastError();
 }
 
-hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s) {
+hipError_t launch_threshold_code(const ImgArgs& a, float theta, hipStream_t s,
+                                 uint32_t* zero_next) {
     const int64_t work = (int64_t)((a.W + 3) / 4) * a.H;
     hipLaunchKernelGGL(k_threshold_code, dim3(stream_grid(work, 256 * 4)), dim3(256), 0, s,
-                       a, theta);
+                       a, theta, zero_next);
     return hipGetLastError();
 }
 

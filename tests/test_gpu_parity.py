@@ -58,7 +58,8 @@ SCHEDULES = [
     (64, 16, 2, 1, 0), (128, 32, 2, 1, 0), (256, 64, 2, 1, 0),
     (64, 32, 3, 1, 0), (128, 16, 3, 1, 0), (256, 128, 3, 1, 0),
     (64, 16, 4, 1, 0), (64, 128, 4, 1, 0), (128, 32, 4, 1, 0),
-    (256, 16, 4, 1, 0), (256, 64, 4, 1, 0), (256, 128, 4, 1, 0),
+    (256, 16, 4, 1, 0), (256, 64, 4, 1, 0), (256, 128, 4, 1, 0), (256, 8, 4, 1, 0),
+    (128, 8, 3, 1, 0),
     (64, 64, 4, 2, 0), (128, 16, 4, 2, 0), (256, 32, 4, 2, 0), (256, 64, 4, 2, 0),
     (256, 64, 4, 3, 0), (256, 32, 4, 3, 0), (256, 48, 4, 3, 0), (256, 96, 4, 3, 0),
     (256, 16, 4, 3, 0), (256, 24, 4, 3, 0),
