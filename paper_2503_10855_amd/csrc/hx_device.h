@@ -36,17 +36,21 @@ __device__ __forceinline__ float lap_from(float ns, float ew, float c) {
     return fmaf(-4.0f, c, ns + ew);
 }
 
-// Sobel pieces of one B row: dx = B(x+1) - B(x-1), sy = ew + 2 B(x).
-__device__ __forceinline__ float sobel_dx(float bl, float br) { return br - bl; }
+// Sobel as two smoothings and two differences:
+//   sy = ew + 2 B(x)          along a row (ew = B(x-1) + B(x+1)),
+//   vs = ns + 2 B(y)          down a column (ns = B(y-1) + B(y+1)),
+//   gx = vs(x+1) - vs(x-1),   gy = sy(y+1) - sy(y-1),
+//   G^2 = gx^2 + gy^2 (the sweep never takes the square root).
+// The sums ew and ns are the Laplacian's, so each is formed once.
 __device__ __forceinline__ float sobel_sy(float ew, float c) {
     return fmaf(2.0f, c, ew);
 }
-// gx = (dx(y-1) + dx(y+1)) + 2 dx(y);  gy = sy(y+1) - sy(y-1);
-// G^2 = gx^2 + gy^2 (the sweep never takes the square root).
-__device__ __forceinline__ float sobel_g2(float dxu, float dxc, float dxd,
-                                         float syu, float syd) {
-    float gx = fmaf(2.0f, dxc, dxu + dxd);
-    float gy = syd - syu;
+__device__ __forceinline__ float sobel_vs(float ns, float c) {
+    return fmaf(2.0f, c, ns);
+}
+__device__ __forceinline__ float sobel_g2(float vsl, float vsr, float syu, float syd) {
+    const float gx = vsr - vsl;
+    const float gy = syd - syu;
     return fmaf(gx, gx, gy * gy);
 }
 

@@ -151,15 +151,17 @@ __global__ __launch_bounds__(256) void k_lap_zero_cross_lds(ImgArgs a, StageBufs
 
 __device__ __forceinline__ float g2_at(const float* B, int64_t op, int y,
                                        int x, int H, int W) {
-    float dxr[3], syr[3];
-    for (int d = 0; d < 3; ++d) {
-        const int yy = clampi(y - 1 + d, 0, H - 1);
-        const float l = at(B, op, yy, x - 1, H, W);
-        const float r = at(B, op, yy, x + 1, H, W);
-        dxr[d] = sobel_dx(l, r);
-        syr[d] = sobel_sy(l + r, at(B, op, yy, x, H, W));
+    // sy on the rows above and below, vs on the columns left and right, each
+    // from B at clamped positions.
+    float sy[2], vs[2];
+    for (int d = 0; d < 2; ++d) {
+        const int yy = y - 1 + 2 * d, xx = x - 1 + 2 * d;
+        sy[d] = sobel_sy(at(B, op, yy, x - 1, H, W) + at(B, op, yy, x + 1, H, W),
+                         at(B, op, yy, x, H, W));
+        vs[d] = sobel_vs(at(B, op, y - 1, xx, H, W) + at(B, op, y + 1, xx, H, W),
+                         at(B, op, y, xx, H, W));
     }
-    return sobel_g2(dxr[0], dxr[1], dxr[2], syr[0], syr[2]);
+    return sobel_g2(vs[0], vs[1], sy[0], sy[1]);
 }
 
 // reduce: HX_REDUCE_TREE folds the max in here (wave shuffle + atomic);

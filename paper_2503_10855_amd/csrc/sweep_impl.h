@@ -8,10 +8,11 @@
 //      blur Bh(v) of the lane's C columns (neighbour columns come from the
 //      adjacent lanes via DPP moves),
 //   B  finishes the vertical blur B(v-R) from the last k Bh rows, and its
-//      row pieces (e+w sums, Sobel dx and sy),
-//   C  forms L and G^2 of row v-R-1 from the last three B rows, and the
-//      signs of L as one 64-bit lane mask per column,
-//   D  forms Z of row v-R-2 from three rows of sign masks and emits its
+//      row pieces (e+w sums, Sobel sy),
+//   C  forms L and G^2 of row v-R-1 from the last three B rows (n+s sums
+//      and Sobel vs down each column), and the row's words of the signs of
+//      L and of its 3-wide windows,
+//   D  forms Z of row v-R-2 from three rows of window words and emits its
 //      output.
 // The first 2R+4 steps fill this pipeline and are unrolled with
 // compile-time stage flags; the remaining `ty` steps (the tile height, a
@@ -21,13 +22,14 @@
 // the same order as the depth-1 stage kernels, so all schedules agree bit
 // for bit.
 //
-// Stage D works on lane masks, i.e. on the scalar unit: a column's signs of
-// L over the wave are one ballot, the 3x3 window's "holds an L > 0" and
-// "holds only L > 0" are ORs and ANDs of three rows of masks and of the
-// masks of the neighbouring columns (a neighbouring lane's column is the
-// mask shifted by one bit), and the mask bit of a pixel is that window test
-// ANDed with the vector compare G^2 > thr2 -- one v_cmp per column for the
-// signs, one per column for the threshold, one v_cndmask per output byte.
+// Stages C and D keep a row's per-column decisions in one 32-bit word per
+// lane, one byte per column (the layout of the lane's mask bytes): the
+// signs of L (0/1), the 3-wide windows' "holds an L > 0" / "holds only
+// L > 0" (OR / AND of the word and its copies shifted by one column, the
+// neighbouring lanes' edge bytes shifted in by one DPP move and one
+// alignbit each), and the threshold G^2 > thr2 as 0x00/0xff bytes (the
+// sign bytes of thr2 - G^2 gathered by v_perm_b32).  Z over three rows is
+// one OR3 and one AND3, and the mask word is Z AND the threshold bytes.
 //
 // Tiles whose whole input window lies inside the image (the common case)
 // run an instantiation with no border logic at all.  The others run one
@@ -114,6 +116,57 @@ __device__ __forceinline__ uint32_t pos_bit(float l) {
     uint32_t r;
     asm("v_med3_i32 %0, %1, 0, 1" : "=v"(r) : "v"(l));
     return r;
+}
+
+// Row words of stage D hold one byte per column of the lane (byte e =
+// column e, bytes C..3 zero).  The low bytes of b[0..C-1] packed so.
+template <int C>
+__device__ __forceinline__ uint32_t col_bytes(const uint32_t (&b)[C]) {
+    uint32_t w = b[0];
+#pragma unroll
+    for (int e = 1; e < C; ++e) w |= b[e] << (8 * e);
+    return w;
+}
+
+// Byte e = 0xff if t[e] has its sign bit set, else 0 (v_perm_b32 selectors
+// 9 and 11 replicate the sign bit of byte 3 of its low / high source).
+template <int C>
+__device__ __forceinline__ uint32_t col_sign_bytes(const float (&t)[C]) {
+    const uint32_t t0 = __float_as_uint(t[0]);
+    if constexpr (C == 1) {
+        return __builtin_amdgcn_perm(t0, t0, 0x0c0c0c09u);
+    } else {
+        const uint32_t lo = __builtin_amdgcn_perm(__float_as_uint(t[1]), t0, 0x0c0c0b09u);
+        if constexpr (C == 2) return lo;
+        else return lo | __builtin_amdgcn_perm(__float_as_uint(t[3]), __float_as_uint(t[2]),
+                                               0x0b090c0cu);
+    }
+}
+
+// A row word shifted by one column, the neighbouring lane's edge column
+// shifted in: byte e of the result is column e-1 (from_left) or e+1
+// (from_right) of the lane's row, counted across lanes.  Lanes at the
+// wave's edges shift in 0 (such columns only feed discarded halo columns).
+// For C < 4 bytes above C-1 of the result are not meaningful.
+template <int C>
+__device__ __forceinline__ uint32_t cols_from_left(uint32_t w) {
+    const uint32_t xl =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+    if constexpr (C == 4) return __builtin_amdgcn_alignbit(w, xl, 24u);
+    else return (w << 8) | (xl >> (8 * (C - 1)));
+}
+template <int C>
+__device__ __forceinline__ uint32_t cols_from_right(uint32_t w) {
+    const uint32_t xr =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+    if constexpr (C == 4) return __builtin_amdgcn_alignbit(xr, w, 8u);
+    else return (w >> 8) | (xr << (8 * (C - 1)));
+}
+
+// The set columns of a mask word (bytes 0/1) as bits 0..C-1.
+__device__ __forceinline__ uint32_t col_nibble(uint32_t mw) {
+    const uint32_t t = mw | (mw >> 7);
+    return (t | (t >> 14)) & 0xfu;
 }
 
 __device__ __forceinline__ float max3f(float a, float b, float c) {
@@ -253,6 +306,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     const int lane = lane_id();
     const int H = a.H, W = a.W;
     const int NS = ty + 2 * HX;
+    const int vlast = y0 - HX + NS - 1;   // the tile's last input row
     const int xs = x0 - HL;
     const int cbase = xs + C * lane;
     // Byte offsets of the lane's first column in an input / mask row.  Only
@@ -317,12 +371,11 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     float bh[P][C];   // horizontal blur rows
     float bb[P][C];   // B rows
     float ew[P][C];   // B(x-1) + B(x+1)
-    float dx[P][C];   // Sobel dx
     float sy[P][C];   // Sobel sy
-    uint32_t hz[P];   // per L row: bit e = the 3-wide window at column e
-                      // holds an L > 0 (bits 0..C-1) / holds only L > 0
-                      // (bits 8..8+C-1)
+    uint32_t ho[P];   // per L row, byte e: the 3-wide window at column e
+    uint32_t ha[P];   // holds an L > 0 (ho) / holds only L > 0 (ha), 0/1
     float g2d[C];     // G^2 of the row waiting for its Z
+    uint32_t tbd = 0; // its threshold bytes (0xff where G^2 > thr2)
     float gacc = 0.0f;
     // The output row of stage D is written one step later, after the next
     // row's L and G^2 (flush_out): its stores are guarded by the lanes that
@@ -336,7 +389,6 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     bool pv = false;
     int vzl = 0;
     uint32_t mwl = 0;
-    uint32_t mbl = 0;   // SM_SPEC: the pending row's set columns (bit e)
     lmask bal = 0;      // SM_SPEC: the lanes of the pending row that set one
     float cdl[C];
     float g2l[C];
@@ -345,10 +397,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         cdl[e] = 0.0f;
         g2l[e] = 0.0f;
     }
-    // The lane's columns inside the image, as a nibble (border variants).
-    uint32_t emask = 0;
+    // The lane's columns inside the image, as 0xff bytes (border variants).
+    uint32_t emw = 0;
 #pragma unroll
-    for (int e = 0; e < C; ++e) emask |= ecol[e] ? (1u << e) : 0u;
+    for (int e = 0; e < C; ++e) emw |= ecol[e] ? (0xffu << (8 * e)) : 0u;
     auto flush_out = [&]() {
         if constexpr (S::NEED_Z) {
             if (pv) {
@@ -384,13 +436,14 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                         const uint32_t idx = sp->n + below;
-                        if ((((bal >> lane) & 1u) != 0u) & (idx < sp->cap)) {
+                        if (__builtin_amdgcn_inverse_ballot_w64(bal) & (idx < sp->cap)) {
                             const gptr<VecF<C>> q =
                                 at_off<VecF<C>>(as_global(sp->code), idx * (uint32_t)(4 * C));
 #pragma unroll
                             for (int e = 0; e < C; ++e) q->v[e] = g2l[e];
-                            *at_off<int32_t>(as_global(sp->row), idx * 4u) = (int32_t)(
-                                ((uint32_t)(vzl - y0) << 10) | ((uint32_t)lane << 4) | mbl);
+                            *at_off<int32_t>(as_global(sp->row), idx * 4u) =
+                                (int32_t)(((uint32_t)(vzl - y0) << 10) |
+                                          ((uint32_t)lane << 4) | col_nibble(mwl));
                         }
                         sp->n += (uint32_t)__builtin_popcountll(bal);
                     }
@@ -412,8 +465,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         constexpr int J1 = (J + P - 1) % P, J2 = (J + P - 2) % P;
         const int v = y0 - HX + s;
         if constexpr (LD == 1) load_row(v + PF, pf[(J + PF) % P]);
-        if constexpr (LD == 2)
-            if (s + PF < NS) load_row(v + PF, pf[(J + PF) % P]);
+        // LD == 2: past the tile's last input row the prefetch repeats that
+        // row (its value is never used): every step loads, so the memory
+        // wait before a row's use counts only the loads issued after it.
+        if constexpr (LD == 2) load_row(min(v + PF, vlast), pf[(J + PF) % P]);
 
         // ---- A: horizontal blur of input row v
         {
@@ -453,7 +508,6 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 const float r = e < C - 1 ? b[e + 1] : br0;
                 bb[J][e] = b[e];
                 ew[J][e] = l + r;
-                dx[J][e] = sobel_dx(l, r);
                 sy[J][e] = sobel_sy(ew[J][e], b[e]);
             }
             if constexpr (BY) {
@@ -461,7 +515,6 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
 #pragma unroll
                     for (int e = 0; e < C; ++e) {
                         bb[J1][e] = bb[J][e];
-                        dx[J1][e] = dx[J][e];
                         sy[J1][e] = sy[J][e];
                     }
                 }
@@ -471,10 +524,20 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         // ---- C: L and G^2 of row vl = v - R - 1
         if constexpr (DC) {
             const int vl = v - R - 1;
-            float g2[C];
+            // ns and vs down each column; gx from the neighbouring
+            // columns' vs (the outer ones from the adjacent lanes).
+            float ns[C], vs[C], g2[C];
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                ns[e] = bb[J2][e] + bb[J][e];
+                vs[e] = sobel_vs(ns[e], bb[J1][e]);
+            }
+            const float vsl0 = lane_fetch<-1>(vs[C - 1]);
+            const float vsr0 = lane_fetch<1>(vs[0]);
 #pragma unroll
             for (int e = 0; e < C; ++e)
-                g2[e] = sobel_g2(dx[J2][e], dx[J1][e], dx[J][e], sy[J2][e], sy[J][e]);
+                g2[e] = sobel_g2(e > 0 ? vs[e - 1] : vsl0, e < C - 1 ? vs[e + 1] : vsr0,
+                                 sy[J2][e], sy[J][e]);
             if constexpr (S::DO_MAX) {
                 if constexpr (!BX && !BY) {
                     // Every row of an interior tile is a real pixel row and
@@ -501,7 +564,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 float l[C];
 #pragma unroll
                 for (int e = 0; e < C; ++e)
-                    l[e] = lap_from(bb[J2][e] + bb[J][e], ew[J1][e], bb[J1][e]);
+                    l[e] = lap_from(ns[e], ew[J1][e], bb[J1][e]);
                 if constexpr (MODE == SM_BGL) {
                     if (row_out) {
                         store_f(fo, vl, l);
@@ -510,29 +573,25 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 }
                 if constexpr (S::NEED_Z) {
                     if constexpr (BX) fix_cols<C, HL, SW>(l, x0, xs, cbase, W);
-                    // Z needs only the sign of L.  One bit per column (L > 0
-                    // exactly when L's bits, read as a signed integer, are
-                    // >= 1: -0 reads as INT_MIN), laid out with the
-                    // neighbouring lanes' outer columns as a (C+2)-bit
-                    // window: bit 0 the left lane's column C-1, bit e+1
-                    // column e, bit C+1 the right lane's column 0.  Then the
-                    // 3-wide window at each column holds an L > 0 (OR of
-                    // three shifts) / only L > 0 (AND of three shifts).
+                    // Z needs only the sign of L: 1 if L > 0 (L's bits,
+                    // read as a signed integer, are >= 1; -0 reads as
+                    // INT_MIN), one byte per column.
                     uint32_t sb[C];
 #pragma unroll
                     for (int e = 0; e < C; ++e) sb[e] = pos_bit(l[e]);
-                    uint32_t ext = (uint32_t)__builtin_amdgcn_mov_dpp(
-                        (int)sb[C - 1], 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
-#pragma unroll
-                    for (int e = 0; e < C; ++e) ext |= sb[e] << (e + 1);
-                    ext |= (uint32_t)__builtin_amdgcn_mov_dpp((int)sb[0], 0x130 /* wave_shl:1 */,
-                                                              0xf, 0xf, true)
-                           << (C + 1);
-                    const uint32_t e1 = ext >> 1, e2 = ext >> 2;
-                    hz[J] = (ext | e1 | e2) | ((ext & e1 & e2) << 8);
+                    const uint32_t sw = col_bytes<C>(sb);
+                    const uint32_t sl = cols_from_left<C>(sw), sr = cols_from_right<C>(sw);
+                    ho[J] = sw | sl | sr;
+                    ha[J] = sw & sl & sr;
                     if constexpr (BY) {
-                        if (vl >= H) hz[J] = hz[J1];
-                        if (vl == 0) hz[J1] = hz[J];
+                        if (vl >= H) {
+                            ho[J] = ho[J1];
+                            ha[J] = ha[J1];
+                        }
+                        if (vl == 0) {
+                            ho[J1] = ho[J];
+                            ha[J1] = ha[J];
+                        }
                     }
                     flush_out();
                     // ---- D: Z of row vz = vl - 1, and the output
@@ -540,28 +599,22 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                         const int vz = vl - 1;
                         if (!BY || ((vz >= y0) & (vz < ylim))) {
                             // Over the three rows: the window holds an L > 0
-                            // (OR of the low bits) and not only L > 0 (AND of
-                            // the high bits, negated).
-                            constexpr uint32_t CM = (1u << C) - 1u;
-                            const uint32_t any = hz[J2] | hz[J1] | hz[J];
-                            const uint32_t all = hz[J2] & hz[J1] & hz[J];
-                            const uint32_t zb = any & ~(all >> 8) & CM;
+                            // and not only L > 0.
+                            const uint32_t any = ho[J2] | ho[J1] | ho[J];
+                            const uint32_t all = ha[J2] & ha[J1] & ha[J];
                             if constexpr (MODE == SM_STORE) {
+                                const uint32_t zw = any & ~all;
 #pragma unroll
                                 for (int e = 0; e < C; ++e)
-                                    cdl[e] = pass1_code((zb >> e) & 1u, g2d[e]);
+                                    cdl[e] = pass1_code((zw >> (8 * e)) & 1u, g2d[e]);
                             } else {
                                 static_assert(C <= 4, "one mask byte per column in a word");
-                                // Mask bit e = Z and G^2 > thr2; the word has
-                                // bit e in byte e (a multiply spreads it).
-                                uint32_t gn = 0;
-#pragma unroll
-                                for (int e = 0; e < C; ++e) gn |= (g2d[e] > thr2) ? (1u << e) : 0u;
-                                const uint32_t mb = zb & gn;
-                                mwl = (mb * 0x00204081u) & 0x01010101u;
+                                // Mask byte e = Z and G^2 > thr2: 0 or 1.
+                                uint32_t mw = any & ~all & tbd;
+                                if constexpr (BX) mw &= emw;
+                                mwl = mw;
                                 if constexpr (MODE == SM_SPEC) {
-                                    mbl = BX ? (mb & emask) : mb;
-                                    bal = __ballot(mbl != 0u);
+                                    bal = __ballot(mw != 0u);
                                     if constexpr (!BX) bal &= out_lanes;
 #pragma unroll
                                     for (int e = 0; e < C; ++e) g2l[e] = g2d[e];
@@ -573,6 +626,15 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                     }
 #pragma unroll
                     for (int e = 0; e < C; ++e) g2d[e] = g2[e];
+                    if constexpr (MODE == SM_MASK || MODE == SM_SPEC) {
+                        // The row's threshold: the sign of thr2 - G^2 is set
+                        // exactly when G^2 > thr2 (a difference of finite
+                        // values is 0 only when they are equal, and then +0).
+                        float t[C];
+#pragma unroll
+                        for (int e = 0; e < C; ++e) t[e] = thr2 - g2[e];
+                        tbd = col_sign_bytes<C>(t);
+                    }
                 }
             }
         }
