@@ -19,13 +19,29 @@ struct Taps {
 };
 
 // Horizontal or vertical pass of the separable blur over k samples
-// v[0..k-1] (v[r] is the centre): a left-to-right fma chain.
+// v[0..k-1] (v[r] is the centre, r = k/2; the taps are symmetric): the
+// centre's product, then for i = 1..r the pair v[r-i] + v[r+i] times its
+// tap, added in that order by fma.  Each output costs k operations, and a
+// sample from a neighbouring lane only ever enters an addition.
+template <int K>
+__device__ __forceinline__ float blur_pair(const float* v, int i) {
+    return v[K / 2 - i] + v[K / 2 + i];
+}
+template <int K>
+__device__ __forceinline__ float blur_from_pairs(float centre, const float* pair,
+                                                 const Taps& t) {
+    constexpr int R = K / 2;
+    float acc = t.g[R] * centre;
+#pragma unroll
+    for (int i = 1; i <= R; ++i) acc = fmaf(t.g[R + i], pair[i - 1], acc);
+    return acc;
+}
 template <int K>
 __device__ __forceinline__ float blur_chain(const float* v, const Taps& t) {
-    float acc = t.g[0] * v[0];
+    float pair[K / 2 > 0 ? K / 2 : 1];
 #pragma unroll
-    for (int i = 1; i < K; ++i) acc = fmaf(t.g[i], v[i], acc);
-    return acc;
+    for (int i = 1; i <= K / 2; ++i) pair[i - 1] = blur_pair<K>(v, i);
+    return blur_from_pairs<K>(v[K / 2], pair, t);
 }
 
 // Pairwise sums that both the Laplacian and the Sobel stage reuse.

@@ -36,6 +36,9 @@ namespace hx {
 #ifndef HX_SWEEP_WAVES
 #define HX_SWEEP_WAVES 3
 #endif
+#ifndef HX_SWEEP_WAVES_SMALL_K
+#define HX_SWEEP_WAVES_SMALL_K HX_SWEEP_WAVES
+#endif
 #ifndef HX_BATCH_WG_WAVES
 #define HX_BATCH_WG_WAVES 1
 #endif
@@ -46,6 +49,9 @@ constexpr int kBTY = HX_BATCH_TY;  // default rows per sweep tile
 // waits for room for all four; with calls in flight on several streams
 // that lets one call's last partial round of tiles overlap the next call.
 constexpr int kWG = HX_BATCH_WG_WAVES;
+// Waves per SIMD the sweep kernels are compiled for (their register cap):
+// the 7-tap blur's longer row ring needs more registers than k <= 5.
+constexpr int sweep_waves(int ks) { return ks <= 5 ? HX_SWEEP_WAVES_SMALL_K : HX_SWEEP_WAVES; }
 
 int batch_sweep_c() { return kBC; }
 int batch_sweep_ty() { return kBTY; }
@@ -109,7 +115,7 @@ __device__ __forceinline__ int global_wave() {
 // image also clears the image's max slot (pass 1 folds into it after this
 // kernel), so SPECULATE needs no reset kernel.
 template <int KS>
-__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(sweep_waves(KS))))
 void k_batch_p0(const uint8_t* __restrict__ table, Taps tp) {
     using S = SweepShape<KS, kBC, SM_MAXONLY>;
     const TableView tv = view(table);
@@ -161,8 +167,11 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
             sp.row = tv.hdr.cand_row + base;
             sp.cap = a.list_cap;
         }
-        sweep_tile<KS, kBC, M1>(a, tp, (it.local % nstrips) * S::OW,
-                                (it.local / nstrips) * a.ty, a.ty, thr2, gmax, &sp);
+        // Odd bands sweep upwards (their halo rows are then read while the
+        // neighbouring bands read them too).
+        const int band = it.local / nstrips;
+        sweep_tile<KS, kBC, M1>(a, tp, (it.local % nstrips) * S::OW, band * a.ty, a.ty, thr2,
+                                gmax, &sp, (band & 1) != 0);
         if constexpr (PASS == HX_PASS_SPECULATE)
             if (lane_id() == 0) as_global(tv.hdr.cand_n)[k] = sp.n;
         gmax = wave_max(gmax);
@@ -174,17 +183,19 @@ __device__ __forceinline__ void batch_p1_body(const uint8_t* __restrict__ table,
 // registers): left alone, the scheduler keeps more rows in flight and
 // the kernels fall to two waves per SIMD, which measured slower.
 template <int KS, int PASS>
-__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(sweep_waves(KS))))
 void k_batch_p1(const uint8_t* __restrict__ table, Taps tp) {
     batch_p1_body<KS, PASS>(table, tp);
 }
 
 template <int KS>
-__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
+__global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(sweep_waves(KS))))
 void k_batch_p1s(const uint8_t* __restrict__ table, Taps tp) {
     batch_p1_body<KS, HX_PASS_SPECULATE>(table, tp);
 }
 
+// Pass 2's mask-only sweep (RECOMPUTE, SPECULATE overflow) keeps the
+// three-wave cap at every k: at four it spills.
 template <int KS, int PASS>
 __global__ __launch_bounds__(64 * kWG) __attribute__((amdgpu_waves_per_eu(HX_SWEEP_WAVES)))
 void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
@@ -272,8 +283,9 @@ void k_batch_p2(const uint8_t* __restrict__ table, Taps tp) {
         } else {
             const int nstrips = (a.W + S::OW - 1) / S::OW;
             float unused = 0.0f;
-            sweep_tile<KS, kBC, SM_MASK>(a, tp, (it.local % nstrips) * S::OW,
-                                         (it.local / nstrips) * a.ty, a.ty, thr2, unused);
+            const int band = it.local / nstrips;
+            sweep_tile<KS, kBC, SM_MASK>(a, tp, (it.local % nstrips) * S::OW, band * a.ty, a.ty,
+                                         thr2, unused, nullptr, (band & 1) != 0);
         }
     }
 }

@@ -122,10 +122,16 @@ __device__ __forceinline__ uint32_t pos_bit(float l) {
 // column e, bytes C..3 zero).  The low bytes of b[0..C-1] packed so.
 template <int C>
 __device__ __forceinline__ uint32_t col_bytes(const uint32_t (&b)[C]) {
-    uint32_t w = b[0];
+    if constexpr (C == 4) {
+        // Two byte gathers (v_perm_b32: selector 0x0c gives a zero byte).
+        return __builtin_amdgcn_perm(b[1], b[0], 0x0c0c0400u) |
+               __builtin_amdgcn_perm(b[3], b[2], 0x04000c0cu);
+    } else {
+        uint32_t w = b[0];
 #pragma unroll
-    for (int e = 1; e < C; ++e) w |= b[e] << (8 * e);
-    return w;
+        for (int e = 1; e < C; ++e) w |= b[e] << (8 * e);
+        return w;
+    }
 }
 
 // Byte e = 0xff if t[e] has its sign bit set, else 0 (v_perm_b32 selectors
@@ -168,6 +174,12 @@ __device__ __forceinline__ uint32_t col_nibble(uint32_t mw) {
     const uint32_t t = mw | (mw >> 7);
     return (t | (t >> 14)) & 0xfu;
 }
+
+// Keeps a value's computation in the current basic block: the DPP move
+// that feeds it can then be folded into it (the compiler folds a move only
+// into uses in its own block, and would otherwise sink some of these uses
+// past the deferred stores' branches).
+__device__ __forceinline__ void keep_here(float& v) { asm volatile("" : "+v"(v)); }
 
 __device__ __forceinline__ float max3f(float a, float b, float c) {
     return __builtin_fmaxf(__builtin_fmaxf(a, b), c);
@@ -285,16 +297,23 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 // SM_MASK and SM_SPEC only.  gmax accumulates G^2 over real image pixels
 // of the tile (per lane; the caller reduces).  sp: SM_SPEC's list of the
 // pixels it set; entries beyond sp->cap are counted but not written.
+// up_req: sweep the tile bottom to top (tiles whose rows lie inside the
+// image only; others always sweep down).  Every stage is symmetric under
+// the flip -- the blur's pairs and the n+s sums add commutatively and gy
+// only changes sign before it is squared -- so both directions give the
+// same bits.  Neighbouring bands that sweep in opposite directions read
+// their shared halo rows at the same time (both at the start, or both at
+// the end of their sweeps), so the second read finds them in L2.
 template <int KS, int C, int MODE, bool BX, bool BY>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
-                                           float& gmax, SpecTile* sp) {
+                                           float& gmax, SpecTile* sp, bool up_req) {
     using S = SweepShape<KS, C, MODE>;
     constexpr int R = S::R, HX = S::HX, HL = S::HL, SW = S::SW, OW = S::OW;
     constexpr int NP = S::NP, P = S::P, PF = S::PF;
 
-    // The blur taps in vector registers: the scalar registers are kept for
-    // the lane masks of stage D and the buffer resources.
+#ifdef HX_TAPS_IN_VGPRS
+    // The blur taps in vector registers (frees scalar registers).
     Taps tv;
 #pragma unroll
     for (int i = 0; i < KS; ++i) {
@@ -302,11 +321,21 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         asm("" : "+v"(g));
         tv.g[i] = g;
     }
+#else
+    // The blur taps stay in scalar registers (kernel arguments): each fma
+    // takes one as its scalar operand, which leaves the vector registers
+    // to the row rings.
+    const Taps& tv = tp;
+#endif
 
     const int lane = lane_id();
     const int H = a.H, W = a.W;
     const int NS = ty + 2 * HX;
-    const int vlast = y0 - HX + NS - 1;   // the tile's last input row
+    // Step t of the sweep reads input row row_at(t).
+    const bool up = !BY && up_req;
+    const int dir = up ? -1 : 1;
+    const int vfirst = up ? y0 + ty - 1 + HX : y0 - HX;
+    auto row_at = [&](int t) { return vfirst + dir * t; };
     const int xs = x0 - HL;
     const int cbase = xs + C * lane;
     // Byte offsets of the lane's first column in an input / mask row.  Only
@@ -378,14 +407,14 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     uint32_t tbd = 0; // its threshold bytes (0xff where G^2 > thr2)
     float gacc = 0.0f;
     // The output row of stage D is written one step later, after the next
-    // row's L and G^2 (flush_out): its stores are guarded by the lanes that
-    // own output columns and, for SM_SPEC, the listing is a branch taken
-    // only when the row set a bit.  Each of those ends a basic block, so
-    // deferring them lets a row's zero-crossing work on the scalar unit share
-    // a block with the following row's vector work, and the two overlap.
+    // row's horizontal blur (flush_out): its stores are guarded by the lanes
+    // that own output columns and, for SM_SPEC, the listing is a branch
+    // taken only when the row set a bit.  Each of those ends a basic block;
+    // deferring them keeps a row's integer work of stage D in one block with
+    // the next row's float work, and the two overlap.
     // Pending: the row (vzl, valid if pv), its mask word (mwl) or pass-1
-    // codes (cdl), and for SM_SPEC per column the lanes that set a bit (pl)
-    // with their G^2 (g2l).
+    // codes (cdl), and for SM_SPEC the lanes that set a bit (bal) with
+    // their G^2 (g2l).
     bool pv = false;
     int vzl = 0;
     uint32_t mwl = 0;
@@ -463,12 +492,12 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         constexpr bool DD = decltype(ddt)::value != 0;
         constexpr int LD = decltype(ldt)::value;
         constexpr int J1 = (J + P - 1) % P, J2 = (J + P - 2) % P;
-        const int v = y0 - HX + s;
-        if constexpr (LD == 1) load_row(v + PF, pf[(J + PF) % P]);
+        const int v = row_at(s);
+        if constexpr (LD == 1) load_row(row_at(s + PF), pf[(J + PF) % P]);
         // LD == 2: past the tile's last input row the prefetch repeats that
         // row (its value is never used): every step loads, so the memory
         // wait before a row's use counts only the loads issued after it.
-        if constexpr (LD == 2) load_row(min(v + PF, vlast), pf[(J + PF) % P]);
+        if constexpr (LD == 2) load_row(row_at(min(s + PF, NS - 1)), pf[(J + PF) % P]);
 
         // ---- A: horizontal blur of input row v
         {
@@ -479,12 +508,27 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 ext[kk + R] = lane_fetch<q>(pf[J][kk - q * C]);
             }, std::make_integer_sequence<int, C + 2 * R>{});
 #pragma unroll
-            for (int e = 0; e < C; ++e) bh[J][e] = blur_chain<KS>(&ext[e], tv);
+            for (int e = 0; e < C; ++e) {
+                // The pairs that take a neighbouring lane's sample stay in
+                // this block, where that sample's DPP move folds into them.
+                float pair[R];
+#pragma unroll
+                for (int i = 1; i <= R; ++i) {
+                    pair[i - 1] = blur_pair<KS>(&ext[e], i);
+                    if (e - i < 0 || e + i >= C) keep_here(pair[i - 1]);
+                }
+                bh[J][e] = blur_from_pairs<KS>(ext[e + R], pair, tv);
+            }
         }
+        // The previous row's output, here: its branches then separate float
+        // work of this row only, and no DPP move of stages B and C is split
+        // from its use (a move whose use lies in another block cannot be
+        // folded into it).
+        flush_out();
 
         // ---- B: vertical blur, row vb = v - R
         if constexpr (DB) {
-            const int vb = v - R;
+            const int vb = v - dir * R;
             float b[C];
 #pragma unroll
             for (int e = 0; e < C; ++e) {
@@ -508,6 +552,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 const float r = e < C - 1 ? b[e + 1] : br0;
                 bb[J][e] = b[e];
                 ew[J][e] = l + r;
+                if (e == 0 || e == C - 1) keep_here(ew[J][e]);
                 sy[J][e] = sobel_sy(ew[J][e], b[e]);
             }
             if constexpr (BY) {
@@ -523,7 +568,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
 
         // ---- C: L and G^2 of row vl = v - R - 1
         if constexpr (DC) {
-            const int vl = v - R - 1;
+            const int vl = v - dir * (R + 1);
             // ns and vs down each column; gx from the neighbouring
             // columns' vs (the outer ones from the adjacent lanes).
             float ns[C], vs[C], g2[C];
@@ -538,6 +583,8 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
             for (int e = 0; e < C; ++e)
                 g2[e] = sobel_g2(e > 0 ? vs[e - 1] : vsl0, e < C - 1 ? vs[e + 1] : vsr0,
                                  sy[J2][e], sy[J][e]);
+            keep_here(g2[0]);
+            if constexpr (C > 1) keep_here(g2[C - 1]);
             if constexpr (S::DO_MAX) {
                 if constexpr (!BX && !BY) {
                     // Every row of an interior tile is a real pixel row and
@@ -593,10 +640,9 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                             ha[J1] = ha[J];
                         }
                     }
-                    flush_out();
                     // ---- D: Z of row vz = vl - 1, and the output
                     if constexpr (DD) {
-                        const int vz = vl - 1;
+                        const int vz = vl - dir;
                         if (!BY || ((vz >= y0) & (vz < ylim))) {
                             // Over the three rows: the window holds an L > 0
                             // and not only L > 0.
@@ -642,7 +688,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
 
     // Prefetch, then the pipeline fill with compile-time stage flags.
 #pragma unroll
-    for (int j = 0; j < PF; ++j) load_row(y0 - HX + j, pf[j]);
+    for (int j = 0; j < PF; ++j) load_row(row_at(j), pf[j]);
     static_for([&](auto st) {
         constexpr int s = decltype(st)::value;
         step(IC<s % P>{}, IC<(s >= 2 * R)>{}, IC<(s >= 2 * R + 2)>{},
@@ -683,7 +729,8 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
 template <int KS, int C, int MODE>
 __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
-                                           float& gmax, SpecTile* sp = nullptr) {
+                                           float& gmax, SpecTile* sp = nullptr,
+                                           bool up = false) {
     using S = SweepShape<KS, C, MODE>;
     const int xs = x0 - S::HL;
     // A tile that reaches the image's bottom runs only the rows the image
@@ -700,13 +747,13 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
     const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
     const bool by = (y0 - S::HX < 0) | (y0 + ty + S::HX > a.H);
     if (!bx & !by)
-        sweep_body<KS, C, MODE, false, false>(a, tp, x0, y0, ty, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, false, false>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
     else if (!bx)
-        sweep_body<KS, C, MODE, false, true>(a, tp, x0, y0, ty, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, false, true>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
     else if (!by)
-        sweep_body<KS, C, MODE, true, false>(a, tp, x0, y0, ty, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, true, false>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
     else
-        sweep_body<KS, C, MODE, true, true>(a, tp, x0, y0, ty, thr2, gmax, sp);
+        sweep_body<KS, C, MODE, true, true>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
 }
 
 }  // namespace hx

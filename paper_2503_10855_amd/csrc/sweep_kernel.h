@@ -18,7 +18,8 @@ __global__ __launch_bounds__(256) void k_sweep(ImgArgs a, Taps tp, float theta, 
     float thr2 = 0.0f;
     if constexpr (MODE == SM_MASK) thr2 = thr2_from(*a.slot, theta);
     float gmax = 0.0f;
-    sweep_tile<KS, C, MODE>(a, tp, bx * S::OW, by * ty, ty, thr2, gmax);
+    // Odd bands sweep upwards (shared halo rows are read at the same time).
+    sweep_tile<KS, C, MODE>(a, tp, bx * S::OW, by * ty, ty, thr2, gmax, nullptr, (by & 1) != 0);
     if constexpr (S::DO_MAX) {
         gmax = wave_max(gmax);
         if (lane_id() == 0) atomic_max_g2(a.slot, gmax);

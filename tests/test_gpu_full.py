@@ -35,7 +35,7 @@ def oracle_all(imgs, ks, sigma):
 
 def check(masks, Ms, imgs, ks, sigma, what):
     outs = oracle_all(imgs, ks, sigma)
-    tot = dict(mismatch=0, band=0, amb=0, exempt_diff=0)
+    tot = dict(mismatch=0, band=0, amb=0, exempt_diff=0, band_diff=0, amb_diff=0)
     for i, (m, M, o) in enumerate(zip(masks, Ms, outs)):
         assert abs(M - o["M"]) <= 1e-5 * o["M"], (what, i, M, o["M"])
         r = parity.compare_mask(m, o, THETA)
@@ -43,8 +43,8 @@ def check(masks, Ms, imgs, ks, sigma, what):
             tot[k] += r[k]
         assert r["mismatch"] == 0, (what, i, r)
     say(f"{what}: {len(imgs)} images, {tot}")
-    # The exemptions allow fp32-vs-fp64 flips; on these inputs none occurs.
-    assert tot["exempt_diff"] == 0, (what, tot)
+    # The exemptions allow fp32-vs-fp64 flips, as rare ones only.
+    assert parity.exempt_bounded(tot), (what, tot)
 
 
 def run_batched(p, imgs):

@@ -71,7 +71,7 @@ def test_random_images_per_image_and_batched(hx, ks, sigma, seed):
                 assert np.array_equal(mb, m1), (i, a.shape, pad)
                 r = parity.compare_mask(mb, o, THETA)
                 assert r["mismatch"] == 0, (i, a.shape, pad, r)
-                assert r["exempt_diff"] == 0, (i, a.shape, pad, r)
+                assert parity.exempt_bounded(r), (i, a.shape, pad, r)
                 M = float(dm[i])
                 assert abs(M - o["M"]) <= parity.REL * o["M"] if o["M"] > 0 else M == 0.0, \
                     (i, a.shape, M, o["M"])

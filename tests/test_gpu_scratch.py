@@ -104,7 +104,7 @@ def test_batch_larger_than_its_table(hx, pass_mode):
     for x, m, M in zip(imgs, got, dm):
         o = oracle.edge_detect(x, 5, 1.0, THETA, stages=True)
         r = parity.compare_mask(m, o, THETA)
-        assert r["mismatch"] == 0 and r["exempt_diff"] == 0, (x.shape, r)
+        assert r["mismatch"] == 0 and parity.exempt_bounded(r), (x.shape, r)
         assert abs(M - o["M"]) <= 1e-5 * max(o["M"], 1e-30), (x.shape, M, o["M"])
 
 

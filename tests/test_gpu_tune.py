@@ -41,8 +41,11 @@ def test_autotune_choose_persist_reload(hx, tmp_path, ks, sigma):
         assert depths == {1, 2, 3, 4} and passes == {1, 2, 3}
     else:
         assert depths == {1}
-    best = min(trials, key=lambda t: t["ms"])
-    assert tuple(best["schedule"]) == tuple(chosen)
+    # The chosen schedule is a fastest trial (the cache prints times to 1e-5
+    # ms, so trials that tie there may be listed in either order).
+    best_ms = min(t["ms"] for t in trials)
+    mine = [t for t in trials if tuple(t["schedule"]) == tuple(chosen)]
+    assert mine and mine[0]["ms"] <= best_ms + 1e-5, (chosen, best_ms, mine)
     # every candidate is a schedule program that compiles to its knobs
     for t in trials:
         assert tuple(hx.compile_schedule(t["text"])) == tuple(t["schedule"]), t
@@ -81,8 +84,11 @@ def test_batch_autotune_choose_persist_reload(hx, tmp_path):
     assert {t["tile_h"] for t in trials} >= {32, 64, 128}
     # Ranked by the time per call with one call in flight per batch context.
     assert all(t["in_flight"] == 4 and t["tput_ms"] > 0 and t["ms"] > 0 for t in trials)
-    best = min(trials, key=lambda t: t["tput_ms"])
-    assert (best["tile_h"], best["pass"]) == (th, pm)
+    # The chosen one is a fastest trial (ties at the printed 1e-5 ms may be
+    # listed in either order).
+    best_ms = min(t["tput_ms"] for t in trials)
+    mine = [t for t in trials if (t["tile_h"], t["pass"]) == (th, pm)]
+    assert mine and mine[0]["tput_ms"] <= best_ms + 1e-5, (th, pm, best_ms, mine)
     for a, b in zip(tuned, per_image):
         assert np.array_equal(a, b)
     for img, m in zip(imgs, tuned):
