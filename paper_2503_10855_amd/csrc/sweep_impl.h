@@ -58,7 +58,10 @@ struct SweepShape {
     static constexpr int HL = ((HX + C - 1) / C) * C;      // left halo
     static constexpr int SW = 64 * C;                      // strip width
     static constexpr int OW = ((SW - HL - HX) / C) * C;    // output width
-    static constexpr int NP = 2 * R + 4;                   // pipeline fill
+    // Rows of halo above and below a tile: blur, Laplacian and zero
+    // crossing need R + 2; blur and Sobel alone (the max-only sweep) R + 1.
+    static constexpr int HY = MODE == SM_MAXONLY ? R + 1 : R + 2;
+    static constexpr int NP = 2 * HY;                      // pipeline fill
     static constexpr int P = 8;                            // ring period
 #ifndef HX_SWEEP_PF
 #define HX_SWEEP_PF 6
@@ -71,7 +74,7 @@ struct SweepShape {
     static constexpr bool DO_MAX = MODE != SM_MASK;
     static constexpr bool EAGER = MODE == SM_MAXONLY;  // see the steady state
     static_assert(KS <= P, "the horizontal-blur ring must hold k rows");
-    static_assert(NP == 2 * HX, "a tile's steps are its rows plus both halos");
+    static_assert(HY <= HX && NP <= 2 * R + 4, "stage D starts after the fill");
 };
 
 // Tile heights are multiples of the ring period.
@@ -309,7 +312,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp, bool up_req) {
     using S = SweepShape<KS, C, MODE>;
-    constexpr int R = S::R, HX = S::HX, HL = S::HL, SW = S::SW, OW = S::OW;
+    constexpr int R = S::R, HY = S::HY, HL = S::HL, SW = S::SW, OW = S::OW;
     constexpr int NP = S::NP, P = S::P, PF = S::PF;
 
 #ifdef HX_TAPS_IN_VGPRS
@@ -330,11 +333,11 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
 
     const int lane = lane_id();
     const int H = a.H, W = a.W;
-    const int NS = ty + 2 * HX;
+    const int NS = ty + 2 * HY;
     // Step t of the sweep reads input row row_at(t).
     const bool up = !BY && up_req;
     const int dir = up ? -1 : 1;
-    const int vfirst = up ? y0 + ty - 1 + HX : y0 - HX;
+    const int vfirst = up ? y0 + ty - 1 + HY : y0 - HY;
     auto row_at = [&](int t) { return vfirst + dir * t; };
     const int xs = x0 - HL;
     const int cbase = xs + C * lane;
@@ -360,8 +363,8 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     const lmask word_lanes = mask_words ? __ballot(lane_out & (cbase + C <= W)) : 0;
 
     // The tile's input rows (clamped into the image), output rows.
-    const int in0 = BY ? max(y0 - HX, 0) : y0 - HX;
-    const int in1 = BY ? min(y0 + ty + HX, H) : y0 + ty + HX;
+    const int in0 = BY ? max(y0 - HY, 0) : y0 - HY;
+    const int in1 = BY ? min(y0 + ty + HY, H) : y0 + ty + HY;
     const RowSpan src(a.src, in0, in1 - in0, a.sp, 4, W);
     const int nout = max(ylim - y0, 1);
     constexpr bool WRITES_MASK = MODE == SM_MASK || MODE == SM_SPEC;
@@ -745,7 +748,7 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                           (C == 4 && (reinterpret_cast<uintptr_t>(a.mask) % 4) == 0 &&
                            (a.mp % 4) == 0);
     const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
-    const bool by = (y0 - S::HX < 0) | (y0 + ty + S::HX > a.H);
+    const bool by = (y0 - S::HY < 0) | (y0 + ty + S::HY > a.H);
     if (!bx & !by)
         sweep_body<KS, C, MODE, false, false>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
     else if (!bx)
