@@ -735,6 +735,9 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                                            float& gmax, SpecTile* sp = nullptr,
                                            bool up = false) {
     using S = SweepShape<KS, C, MODE>;
+    // A tile must start inside the image: its row spans are built from
+    // the rows it covers there.
+    if (y0 >= a.H || x0 >= a.W) return;
     const int xs = x0 - S::HL;
     // A tile that reaches the image's bottom runs only the rows the image
     // still has, rounded up to the row step (its output rows are the same;
