@@ -307,7 +307,13 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 // same bits.  Neighbouring bands that sweep in opposite directions read
 // their shared halo rows at the same time (both at the start, or both at
 // the end of their sweeps), so the second read finds them in L2.
-template <int KS, int C, int MODE, bool BX, bool BY>
+// BL (with !BX, C = 4): the tile's only column border is the image's left
+// edge, and its rows are aligned: the vector path runs, and the lane just
+// left of column 0 -- the only outside lane whose values reach an output --
+// has its input samples, its B and its L replaced by column 0's (the
+// clamped-coordinate rule per stage), 6 operations per row instead of the
+// border variant's per-element loads and column fixes.
+template <int KS, int C, int MODE, bool BX, bool BY, bool BL = false>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp, bool up_req) {
@@ -344,7 +350,11 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // Byte offsets of the lane's first column in an input / mask row.  Only
     // lanes inside the image (or, in the border variants, with clamped
     // columns) ever access memory through them.
-    const uint32_t off_in = (uint32_t)cbase * 4u;
+    static_assert(!BL || (!BX && C == 4 && S::HL == 4), "BL: one lane left of column 0");
+    // BL: lanes left of column 0 read columns 0..C-1 (their own values are
+    // replaced or unused), so every access stays inside the image.
+    const uint32_t off_in = (BL && cbase < 0) ? 0u : (uint32_t)cbase * 4u;
+    const bool edge_lane = BL && lane == HL / C - 1;
     const uint32_t off_m = (uint32_t)cbase;
     const int ylim = min(y0 + ty, H);
     const bool lane_out = (cbase >= x0) & (cbase < x0 + OW);
@@ -381,6 +391,12 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
         const int row = BY ? clampi(v, 0, H - 1) : v;
         if constexpr (!BX) {
             span_load<C>(src, row, off_in, dst);
+            if constexpr (BL) {
+                // The edge lane loaded columns 0..C-1: its samples of
+                // columns -C..-1 are column 0's.
+#pragma unroll
+                for (int e = 1; e < C; ++e) dst[e] = edge_lane ? dst[0] : dst[e];
+            }
         } else {
 #pragma unroll
             for (int e = 0; e < C; ++e)
@@ -547,6 +563,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 }
             }
             if constexpr (BX) fix_cols<C, HL, SW>(b, x0, xs, cbase, W);
+            if constexpr (BL) {
+                const float b0 = lane_fetch<1>(b[0]);
+                b[C - 1] = edge_lane ? b0 : b[C - 1];
+            }
             const float bl0 = lane_fetch<-1>(b[C - 1]);
             const float br0 = lane_fetch<1>(b[0]);
 #pragma unroll
@@ -623,6 +643,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 }
                 if constexpr (S::NEED_Z) {
                     if constexpr (BX) fix_cols<C, HL, SW>(l, x0, xs, cbase, W);
+                    if constexpr (BL) {
+                        const float l0 = lane_fetch<1>(l[0]);
+                        l[C - 1] = edge_lane ? l0 : l[C - 1];
+                    }
                     // Z needs only the sign of L: 1 if L > 0 (L's bits,
                     // read as a signed integer, are >= 1; -0 reads as
                     // INT_MIN), one byte per column.
@@ -751,7 +775,20 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                           (C == 4 && (reinterpret_cast<uintptr_t>(a.mask) % 4) == 0 &&
                            (a.mp % 4) == 0);
     const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
+    // Left border only, aligned rows: the vector path with the edge lane's
+    // values fixed (C = 4 and a one-lane left halo, i.e. k <= 5).
+    constexpr bool kHasBL = C == 4 && S::HL == 4;
+    const bool bl = kHasBL && (xs < 0) & (xs + S::SW <= a.W) & vec_ok & mask_vec;
     const bool by = (y0 - S::HY < 0) | (y0 + ty + S::HY > a.H);
+    if constexpr (kHasBL) {
+        if (bl) {
+            if (!by)
+                sweep_body<KS, C, MODE, false, false, kHasBL>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
+            else
+                sweep_body<KS, C, MODE, false, true, kHasBL>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
+            return;
+        }
+    }
     if (!bx & !by)
         sweep_body<KS, C, MODE, false, false>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
     else if (!bx)
