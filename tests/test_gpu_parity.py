@@ -51,7 +51,8 @@ def assert_mask(mask, o, what=""):
 # Sizes spanning several sweep strips/bands plus ragged tails, and the
 # degenerate shapes of the method (one row, one column, one pixel).
 SIZES = [(1, 1), (1, 7), (7, 1), (2, 2), (5, 5), (3, 300), (67, 300),
-         (130, 517), (256, 256), (64, 249), (65, 250), (200, 1000), (300, 61)]
+         (130, 517), (256, 256), (64, 249), (65, 250), (66, 252), (67, 253),
+         (200, 1000), (300, 61)]
 
 SCHEDULES = [
     (16, 16, 1, 1, 0), (32, 16, 1, 1, 0), (64, 32, 1, 1, 0), (16, 32, 1, 1, 0),
@@ -365,7 +366,7 @@ FUSED_STAGE_SCHEDULES = [
 
 @pytest.mark.parametrize("ks,sigma", [(5, 1.0), (7, 1.5), (3, 0.8)])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (3, 300), (130, 517),
-                                   (256, 256), (70, 1100)])
+                                   (256, 256), (70, 1100), (40, 251), (40, 252)])
 def test_fused_depth_stages(hx, shape, ks, sigma):
     """The stage planes the fused depths keep in memory -- B, Z and G at
     depth 2 (its register sweep writes B and G^2, its LDS kernel Z), L, Z
