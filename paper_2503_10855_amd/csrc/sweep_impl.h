@@ -312,8 +312,13 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 // left of column 0 -- the only outside lane whose values reach an output --
 // has its input samples, its B and its L replaced by column 0's (the
 // clamped-coordinate rule per stage), 6 operations per row instead of the
-// border variant's per-element loads and column fixes.
-template <int KS, int C, int MODE, bool BX, bool BY, bool BL = false>
+// border variant's per-element loads and column fixes.  BR (with !BX,
+// C = 4, W a multiple of 4): likewise for a tile whose only column border
+// is the image's right edge: lanes right of column W-1 read columns
+// W-4..W-1, and the first of them (the only one whose values reach an
+// output) has its samples, B and L replaced by column W-1's; lanes right
+// of the edge neither write nor count toward the max.
+template <int KS, int C, int MODE, bool BX, bool BY, bool BL = false, bool BR = false>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp, bool up_req) {
@@ -351,16 +356,22 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // lanes inside the image (or, in the border variants, with clamped
     // columns) ever access memory through them.
     static_assert(!BL || (!BX && C == 4 && S::HL == 4), "BL: one lane left of column 0");
-    // BL: lanes left of column 0 read columns 0..C-1 (their own values are
-    // replaced or unused), so every access stays inside the image.
-    const uint32_t off_in = (BL && cbase < 0) ? 0u : (uint32_t)cbase * 4u;
+    static_assert(!BR || (!BX && !BL && C == 4), "BR: whole lanes right of column W-1");
+    // BL: lanes left of column 0 read columns 0..C-1, BR: lanes right of
+    // column W-1 read columns W-C..W-1 (their own values are replaced or
+    // unused), so every access stays inside the image.
+    const uint32_t off_in = (BL && cbase < 0)        ? 0u
+                            : (BR && cbase + C > W) ? (uint32_t)(W - C) * 4u
+                                                    : (uint32_t)cbase * 4u;
     const bool edge_lane = BL && lane == HL / C - 1;
+    const bool edge_lane_r = BR && cbase == W;
     const uint32_t off_m = (uint32_t)cbase;
     const int ylim = min(y0 + ty, H);
-    const bool lane_out = (cbase >= x0) & (cbase < x0 + OW);
+    const bool lane_out = (cbase >= x0) & (cbase < x0 + OW) & (!BR || cbase + C <= W);
     // Lanes whose every column has a valid G^2 (its neighbourhood lies in
     // the strip); outside the border variants those are all real pixels.
-    const bool gvalid = (cbase >= xs + R + 1) & (cbase + C <= xs + SW - R - 1);
+    const bool gvalid = (cbase >= xs + R + 1) & (cbase + C <= xs + SW - R - 1) &
+                        (!BR || cbase + C <= W);
     bool ecol[C];
 #pragma unroll
     for (int e = 0; e < C; ++e) ecol[e] = lane_out & (cbase + e < W);
@@ -396,6 +407,12 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 // columns -C..-1 are column 0's.
 #pragma unroll
                 for (int e = 1; e < C; ++e) dst[e] = edge_lane ? dst[0] : dst[e];
+            }
+            if constexpr (BR) {
+                // The right edge lane loaded columns W-C..W-1: its samples
+                // of columns W..W+C-1 are column W-1's.
+#pragma unroll
+                for (int e = 0; e < C - 1; ++e) dst[e] = edge_lane_r ? dst[C - 1] : dst[e];
             }
         } else {
 #pragma unroll
@@ -567,6 +584,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 const float b0 = lane_fetch<1>(b[0]);
                 b[C - 1] = edge_lane ? b0 : b[C - 1];
             }
+            if constexpr (BR) {
+                const float bw = lane_fetch<-1>(b[C - 1]);
+                b[0] = edge_lane_r ? bw : b[0];
+            }
             const float bl0 = lane_fetch<-1>(b[C - 1]);
             const float br0 = lane_fetch<1>(b[0]);
 #pragma unroll
@@ -646,6 +667,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                     if constexpr (BL) {
                         const float l0 = lane_fetch<1>(l[0]);
                         l[C - 1] = edge_lane ? l0 : l[C - 1];
+                    }
+                    if constexpr (BR) {
+                        const float lw = lane_fetch<-1>(l[C - 1]);
+                        l[0] = edge_lane_r ? lw : l[0];
                     }
                     // Z needs only the sign of L: 1 if L > 0 (L's bits,
                     // read as a signed integer, are >= 1; -0 reads as
@@ -779,6 +804,10 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
     // values fixed (C = 4 and a one-lane left halo, i.e. k <= 5).
     constexpr bool kHasBL = C == 4 && S::HL == 4;
     const bool bl = kHasBL && (xs < 0) & (xs + S::SW <= a.W) & vec_ok & mask_vec;
+    // Right border only, aligned rows and a width that is a multiple of 4.
+    constexpr bool kHasBR = C == 4;
+    const bool br = kHasBR && (xs >= 0) & (xs + S::SW > a.W) & ((a.W % C) == 0) & vec_ok &
+                    mask_vec;
     const bool by = (y0 - S::HY < 0) | (y0 + ty + S::HY > a.H);
     if constexpr (kHasBL) {
         if (bl) {
@@ -786,6 +815,17 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                 sweep_body<KS, C, MODE, false, false, kHasBL>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
             else
                 sweep_body<KS, C, MODE, false, true, kHasBL>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
+            return;
+        }
+    }
+    if constexpr (kHasBR) {
+        if (br) {
+            if (!by)
+                sweep_body<KS, C, MODE, false, false, false, kHasBR>(a, tp, x0, y0, ty, thr2,
+                                                                     gmax, sp, up);
+            else
+                sweep_body<KS, C, MODE, false, true, false, kHasBR>(a, tp, x0, y0, ty, thr2,
+                                                                    gmax, sp, up);
             return;
         }
     }
