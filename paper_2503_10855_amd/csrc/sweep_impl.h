@@ -318,7 +318,8 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 // W-4..W-1, and the first of them (the only one whose values reach an
 // output) has its samples, B and L replaced by column W-1's; lanes right
 // of the edge neither write nor count toward the max.
-template <int KS, int C, int MODE, bool BX, bool BY, bool BL = false, bool BR = false>
+template <int KS, int C, int MODE, bool BX, bool BY, bool BL = false, bool BR = false,
+          bool BA = false>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp, bool up_req) {
@@ -357,6 +358,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // columns) ever access memory through them.
     static_assert(!BL || (!BX && C == 4 && S::HL == 4), "BL: one lane left of column 0");
     static_assert(!BR || (!BX && !BL && C == 4), "BR: whole lanes right of column W-1");
+    static_assert(!BA || (!BX && !BR && C == 4 && (MODE == SM_MASK || MODE == SM_SPEC)),
+                  "BA: vector rows with mask rows that are not word aligned");
+    static_assert(C != 4 || (S::HL % 4 == 0 && S::OW % 4 == 0),
+                  "a lane's first column is a multiple of 4 from the row start");
     // BL: lanes left of column 0 read columns 0..C-1, BR: lanes right of
     // column W-1 read columns W-C..W-1 (their own values are replaced or
     // unused), so every access stays inside the image.
@@ -393,6 +398,12 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     constexpr bool WRITES_G = MODE == SM_BG || MODE == SM_BGL;
     const RowSpan msk(WRITES_MASK ? (const void*)a.mask : (const void*)a.src, y0, nout,
                       WRITES_MASK ? a.mp : 0, 1, W);
+    // BA: the low two address bits of the tile's first mask row (a lane's
+    // word then starts at those bits plus the row's offset, since its first
+    // column is a multiple of 4).
+    const uint32_t mlo =
+        BA ? (uint32_t)(reinterpret_cast<uintptr_t>(a.mask) + (uint64_t)y0 * (uint64_t)a.mp) & 3u
+           : 0u;
     const RowSpan fo(WRITES_F ? (const void*)a.fout : (const void*)a.src, y0, nout,
                      WRITES_F ? a.op : 0, 4, W);
     const RowSpan go(WRITES_G ? (const void*)a.g2 : (const void*)a.src, y0, nout,
@@ -472,10 +483,35 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 if constexpr (MODE == SM_STORE) {
                     store_f(fo, vzl, cdl);
                 } else {
-                    if constexpr (!BX && C == 4) {
+                    if constexpr (!BX && C == 4 && !BA) {
                         if (__builtin_amdgcn_inverse_ballot_w64(out_lanes))
                             __builtin_amdgcn_raw_buffer_store_b32(mwl, msk.r, off_m,
                                                                   msk.soff(vzl), 0);
+                    } else if constexpr (BA) {
+                        // Mask rows that are not word aligned: the row's
+                        // alignment is the same for every lane, so the
+                        // word goes out as naturally aligned pieces (one
+                        // word, two halves, or byte + half + byte).
+                        const uint32_t so = msk.soff(vzl);
+                        const uint32_t rem = (mlo + so) & 3u;
+                        if (__builtin_amdgcn_inverse_ballot_w64(out_lanes)) {
+                            if (rem == 0u) {
+                                __builtin_amdgcn_raw_buffer_store_b32(mwl, msk.r, off_m, so, 0);
+                            } else if (rem == 2u) {
+                                __builtin_amdgcn_raw_buffer_store_b16(
+                                    (unsigned short)(mwl & 0xffffu), msk.r, off_m, so, 0);
+                                __builtin_amdgcn_raw_buffer_store_b16(
+                                    (unsigned short)(mwl >> 16), msk.r, off_m + 2u, so, 0);
+                            } else {
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (unsigned char)(mwl & 0xffu), msk.r, off_m, so, 0);
+                                __builtin_amdgcn_raw_buffer_store_b16(
+                                    (unsigned short)((mwl >> 8) & 0xffffu), msk.r, off_m + 1u,
+                                    so, 0);
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (unsigned char)(mwl >> 24), msk.r, off_m + 3u, so, 0);
+                            }
+                        }
                     } else {
                         // Whole words for the lanes whose C columns are all
                         // inside the image (when mask rows are word
@@ -792,25 +828,45 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
     // still has, rounded up to the row step (its output rows are the same;
     // a full-height sweep would compute up to ty - 8 rows of clamped rows).
     ty = min(ty, (a.H - y0 + kSweepRowStep - 1) / kSweepRowStep * kSweepRowStep);
-    // Vector rows: input rows that start on 4C-byte boundaries and, for the
-    // mask-writing modes, mask rows that start on 4-byte boundaries.
-    const bool vec_ok =
-        ((reinterpret_cast<uintptr_t>(a.src) % (4 * C)) == 0) & ((a.sp % C) == 0);
-    const bool mask_vec = !(MODE == SM_MASK || MODE == SM_SPEC) ||
-                          (C == 4 && (reinterpret_cast<uintptr_t>(a.mask) % 4) == 0 &&
-                           (a.mp % 4) == 0);
+    // Vector rows.  Input rows that start on 4C-byte boundaries always take
+    // them; with C = 4, in the modes that write no float plane, rows that
+    // start on a word boundary do too (a 16-byte load needs only a 4-byte
+    // aligned address; such a row only touches one more cache line per
+    // wave).  Mask rows that are not word aligned take the BA variant,
+    // which stores each lane's mask word as aligned pieces.
+    constexpr bool WRITES_MASK = MODE == SM_MASK || MODE == SM_SPEC;
+    constexpr bool WRITES_F = MODE == SM_STORE || MODE == SM_BG || MODE == SM_BGL;
+    const bool src_al = ((reinterpret_cast<uintptr_t>(a.src) % (4 * C)) == 0) & ((a.sp % C) == 0);
+    const bool vec_ok = (C == 4 && !WRITES_F) ? (reinterpret_cast<uintptr_t>(a.src) % 4) == 0
+                                              : src_al;
+    const bool mask_al = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
+    constexpr bool kHasBA = C == 4 && WRITES_MASK;
+    const bool mask_vec = !WRITES_MASK || C == 4;
+    const bool ba = kHasBA && !mask_al;
     const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
-    // Left border only, aligned rows: the vector path with the edge lane's
+    // Left border only, vector rows: the vector path with the edge lane's
     // values fixed (C = 4 and a one-lane left halo, i.e. k <= 5).
     constexpr bool kHasBL = C == 4 && S::HL == 4;
     const bool bl = kHasBL && (xs < 0) & (xs + S::SW <= a.W) & vec_ok & mask_vec;
-    // Right border only, aligned rows and a width that is a multiple of 4.
+    // Right border only, 4C-byte aligned input rows, word-aligned mask rows
+    // and a width that is a multiple of 4.
     constexpr bool kHasBR = C == 4;
-    const bool br = kHasBR && (xs >= 0) & (xs + S::SW > a.W) & ((a.W % C) == 0) & vec_ok &
-                    mask_vec;
+    const bool br = kHasBR && (xs >= 0) & (xs + S::SW > a.W) & ((a.W % C) == 0) & src_al &
+                    (!WRITES_MASK || mask_al);
     const bool by = (y0 - S::HY < 0) | (y0 + ty + S::HY > a.H);
     if constexpr (kHasBL) {
         if (bl) {
+            if constexpr (kHasBA) {
+                if (ba) {
+                    if (!by)
+                        sweep_body<KS, C, MODE, false, false, true, false, true>(
+                            a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                    else
+                        sweep_body<KS, C, MODE, false, true, true, false, true>(
+                            a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                    return;
+                }
+            }
             if (!by)
                 sweep_body<KS, C, MODE, false, false, kHasBL>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
             else
@@ -826,6 +882,17 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
             else
                 sweep_body<KS, C, MODE, false, true, false, kHasBR>(a, tp, x0, y0, ty, thr2,
                                                                     gmax, sp, up);
+            return;
+        }
+    }
+    if constexpr (kHasBA) {
+        if (!bx & ba) {
+            if (!by)
+                sweep_body<KS, C, MODE, false, false, false, false, true>(a, tp, x0, y0, ty, thr2,
+                                                                          gmax, sp, up);
+            else
+                sweep_body<KS, C, MODE, false, true, false, false, true>(a, tp, x0, y0, ty, thr2,
+                                                                         gmax, sp, up);
             return;
         }
     }
