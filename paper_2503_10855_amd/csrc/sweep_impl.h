@@ -319,7 +319,7 @@ __device__ __forceinline__ void fix_cols(float (&x)[C], int x0, int xs,
 // output) has its samples, B and L replaced by column W-1's; lanes right
 // of the edge neither write nor count toward the max.
 template <int KS, int C, int MODE, bool BX, bool BY, bool BL = false, bool BR = false,
-          bool BA = false>
+          bool BA = false, bool BQ = false>
 __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                            int x0, int y0, int ty, float thr2,
                                            float& gmax, SpecTile* sp, bool up_req) {
@@ -358,10 +358,12 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // columns) ever access memory through them.
     static_assert(!BL || (!BX && C == 4 && S::HL == 4), "BL: one lane left of column 0");
     static_assert(!BR || (!BX && !BL && C == 4), "BR: whole lanes right of column W-1");
-    static_assert(!BA || (!BX && !BR && C == 4 && (MODE == SM_MASK || MODE == SM_SPEC)),
+    static_assert(!BA || (!BX && (!BR || BQ) && C == 4 && (MODE == SM_MASK || MODE == SM_SPEC)),
                   "BA: vector rows with mask rows that are not word aligned");
     static_assert(C != 4 || (S::HL % 4 == 0 && S::OW % 4 == 0),
                   "a lane's first column is a multiple of 4 from the row start");
+    static_assert(!BQ || (BR && MODE != SM_STORE && MODE != SM_BG && MODE != SM_BGL),
+                  "BQ: a right edge inside a lane");
     // BL: lanes left of column 0 read columns 0..C-1, BR: lanes right of
     // column W-1 read columns W-C..W-1 (their own values are replaced or
     // unused), so every access stays inside the image.
@@ -369,19 +371,45 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                             : (BR && cbase + C > W) ? (uint32_t)(W - C) * 4u
                                                     : (uint32_t)cbase * 4u;
     const bool edge_lane = BL && lane == HL / C - 1;
-    const bool edge_lane_r = BR && cbase == W;
+    // BQ (W not a multiple of 4): the straddling lane holds columns
+    // W-wr..W-wr+3, of which the first wr are inside the image; the lane
+    // after it plays the edge lane's part.
+    const int wr = W & 3;
+    const bool strad = BQ && (cbase < W) && (cbase + C > W);
+    const bool edge_lane_r = BR && (BQ ? (cbase >= W) & (cbase < W + C) : cbase == W);
     const uint32_t off_m = (uint32_t)cbase;
     const int ylim = min(y0 + ty, H);
-    const bool lane_out = (cbase >= x0) & (cbase < x0 + OW) & (!BR || cbase + C <= W);
+    const bool lane_out = (cbase >= x0) & (cbase < x0 + OW) &
+                          (!BR || (BQ ? cbase < W : cbase + C <= W));
     // Lanes whose every column has a valid G^2 (its neighbourhood lies in
     // the strip); outside the border variants those are all real pixels.
     const bool gvalid = (cbase >= xs + R + 1) & (cbase + C <= xs + SW - R - 1) &
-                        (!BR || cbase + C <= W);
+                        (!BR || (BQ ? cbase < W : cbase + C <= W));
     bool ecol[C];
 #pragma unroll
     for (int e = 0; e < C; ++e) ecol[e] = lane_out & (cbase + e < W);
-    // The lanes that own output columns, as a mask (interior tiles).
-    const lmask out_lanes = __ballot(lane_out);
+    // The lanes that own output columns, as a mask (interior tiles); with
+    // BQ the straddling lane is apart (it writes single bytes).
+    const lmask out_lanes = __ballot(lane_out & (!BQ || cbase + C <= W));
+    const bool strad_out = BQ && lane_out && strad;
+    const lmask strad_lanes = BQ ? __ballot(strad_out) : 0;
+    // BQ: the straddling lane's per-column selections (wr is uniform):
+    // samples from the loaded columns W-4..W-1, and the columns at and past
+    // W that take column W-1's B and L (fixB[e]) or carry no G^2 (gkill[e]).
+    bool s0v1 = false, s0v2 = false, s0v3 = false, s1v2 = false, s1v3 = false;
+    bool fixB[C], gkill[C];
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        fixB[e] = strad && (e > 0) && (wr == e);
+        gkill[e] = strad && (e >= wr);
+    }
+    if constexpr (BQ) {
+        s0v1 = strad && wr == 3;
+        s0v2 = strad && wr == 2;
+        s0v3 = strad && wr == 1;
+        s1v2 = strad && wr == 3;
+        s1v3 = strad && wr <= 2;
+    }
     // Border variants: the lanes that may write their mask row as one word
     // (all C columns inside the image, word-aligned mask rows).
     const bool mask_words = (C == 4) && ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) &&
@@ -424,6 +452,14 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 // of columns W..W+C-1 are column W-1's.
 #pragma unroll
                 for (int e = 0; e < C - 1; ++e) dst[e] = edge_lane_r ? dst[C - 1] : dst[e];
+            }
+            if constexpr (BQ) {
+                // The straddling lane loaded columns W-4..W-1: column
+                // W-wr+e is loaded column min(4-wr+e, 3).
+                const float v1 = dst[1], v2 = dst[2], v3 = dst[3];
+                dst[0] = s0v3 ? v3 : (s0v2 ? v2 : (s0v1 ? v1 : dst[0]));
+                dst[1] = s1v3 ? v3 : (s1v2 ? v2 : dst[1]);
+                dst[2] = strad ? v3 : dst[2];
             }
         } else {
 #pragma unroll
@@ -528,6 +564,21 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                         msk.soff(vzl), 0);
                         }
                     }
+                    if constexpr (BQ) {
+                        // The straddling lane: its wr columns inside the
+                        // image, one byte each.
+                        if (strad_out) {
+                            const uint32_t so = msk.soff(vzl);
+                            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(mwl & 0xffu),
+                                                                 msk.r, off_m, so, 0);
+                            if (wr > 1)
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (unsigned char)((mwl >> 8) & 0xffu), msk.r, off_m + 1u, so, 0);
+                            if (wr > 2)
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (unsigned char)((mwl >> 16) & 0xffu), msk.r, off_m + 2u, so, 0);
+                        }
+                    }
                 }
                 if constexpr (MODE == SM_SPEC) {
                     // The lanes that set a bit in the row, packed in lane
@@ -620,9 +671,14 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 const float b0 = lane_fetch<1>(b[0]);
                 b[C - 1] = edge_lane ? b0 : b[C - 1];
             }
-            if constexpr (BR) {
+            if constexpr (BR && !BQ) {
                 const float bw = lane_fetch<-1>(b[C - 1]);
                 b[0] = edge_lane_r ? bw : b[0];
+            }
+            if constexpr (BQ) {
+                // Column W of the straddling lane takes column W-1's B.
+#pragma unroll
+                for (int e = 1; e < C; ++e) b[e] = fixB[e] ? b[e - 1] : b[e];
             }
             const float bl0 = lane_fetch<-1>(b[C - 1]);
             const float br0 = lane_fetch<1>(b[0]);
@@ -669,6 +725,10 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                 if constexpr (!BX && !BY) {
                     // Every row of an interior tile is a real pixel row and
                     // max is idempotent: no per-row masking needed.
+                    if constexpr (BQ) {
+#pragma unroll
+                        for (int e = 1; e < C; ++e) g2[e] = gkill[e] ? 0.0f : g2[e];
+                    }
 #pragma unroll
                     for (int e = 0; e + 1 < C; e += 2) gacc = max3f(gacc, g2[e], g2[e + 1]);
                     if constexpr (C % 2) gacc = __builtin_fmaxf(gacc, g2[C - 1]);
@@ -704,9 +764,13 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                         const float l0 = lane_fetch<1>(l[0]);
                         l[C - 1] = edge_lane ? l0 : l[C - 1];
                     }
-                    if constexpr (BR) {
+                    if constexpr (BR && !BQ) {
                         const float lw = lane_fetch<-1>(l[C - 1]);
                         l[0] = edge_lane_r ? lw : l[0];
+                    }
+                    if constexpr (BQ) {
+#pragma unroll
+                        for (int e = 1; e < C; ++e) l[e] = fixB[e] ? l[e - 1] : l[e];
                     }
                     // Z needs only the sign of L: 1 if L > 0 (L's bits,
                     // read as a signed integer, are >= 1; -0 reads as
@@ -745,11 +809,11 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
                                 static_assert(C <= 4, "one mask byte per column in a word");
                                 // Mask byte e = Z and G^2 > thr2: 0 or 1.
                                 uint32_t mw = any & ~all & tbd;
-                                if constexpr (BX) mw &= emw;
+                                if constexpr (BX || BQ) mw &= emw;
                                 mwl = mw;
                                 if constexpr (MODE == SM_SPEC) {
                                     bal = __ballot(mw != 0u);
-                                    if constexpr (!BX) bal &= out_lanes;
+                                    if constexpr (!BX) bal &= out_lanes | strad_lanes;
 #pragma unroll
                                     for (int e = 0; e < C; ++e) g2l[e] = g2d[e];
                                 }
@@ -853,7 +917,32 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
     constexpr bool kHasBR = C == 4;
     const bool br = kHasBR && (xs >= 0) & (xs + S::SW > a.W) & ((a.W % C) == 0) & src_al &
                     (!WRITES_MASK || mask_al);
+    // Right border only, vector rows, W not a multiple of 4 (BQ): the
+    // straddling lane and the lane after it must both lie in the strip.
+    constexpr bool kHasBQ = C == 4 && !WRITES_F;
+    const bool bq = kHasBQ && (xs >= 0) & (xs + S::SW > a.W) & ((a.W % C) != 0) &
+                    (a.W - (a.W % C) + 2 * C <= xs + S::SW) & vec_ok & mask_vec;
     const bool by = (y0 - S::HY < 0) | (y0 + ty + S::HY > a.H);
+    if constexpr (kHasBQ) {
+        if (bq) {
+            if (!ba) {
+                if (!by)
+                    sweep_body<KS, C, MODE, false, false, false, true, false, true>(
+                        a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                else
+                    sweep_body<KS, C, MODE, false, true, false, true, false, true>(
+                        a, tp, x0, y0, ty, thr2, gmax, sp, up);
+            } else if constexpr (kHasBA) {
+                if (!by)
+                    sweep_body<KS, C, MODE, false, false, false, true, true, true>(
+                        a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                else
+                    sweep_body<KS, C, MODE, false, true, false, true, true, true>(
+                        a, tp, x0, y0, ty, thr2, gmax, sp, up);
+            }
+            return;
+        }
+    }
     if constexpr (kHasBL) {
         if (bl) {
             if constexpr (kHasBA) {
