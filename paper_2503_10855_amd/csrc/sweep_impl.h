@@ -357,7 +357,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // lanes inside the image (or, in the border variants, with clamped
     // columns) ever access memory through them.
     static_assert(!BL || (!BX && C == 4 && S::HL == 4), "BL: one lane left of column 0");
-    static_assert(!BR || (!BX && !BL && C == 4), "BR: whole lanes right of column W-1");
+    static_assert(!BR || (!BX && C == 4), "BR: whole lanes right of column W-1");
     static_assert(!BA || (!BX && (!BR || BQ) && C == 4 && (MODE == SM_MASK || MODE == SM_SPEC)),
                   "BA: vector rows with mask rows that are not word aligned");
     static_assert(C != 4 || (S::HL % 4 == 0 && S::OW % 4 == 0),
@@ -941,6 +941,42 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                         a, tp, x0, y0, ty, thr2, gmax, sp, up);
             }
             return;
+        }
+    }
+    // Both borders in one strip (an image narrower than the strip, k <= 5,
+    // modes that write no float plane): the left edge lane's fixes and the
+    // right edge's together; they touch different lanes once W >= 2C.
+    if constexpr (kHasBL && kHasBQ) {
+        const bool bn = (xs < 0) & (xs + S::SW > a.W) & (a.W >= 2 * C) & vec_ok & mask_vec;
+        if (bn) {
+            if ((a.W % C) == 0) {
+                if (src_al & (!WRITES_MASK || mask_al) & (a.W + C <= xs + S::SW)) {
+                    if (!by)
+                        sweep_body<KS, C, MODE, false, false, true, true>(a, tp, x0, y0, ty, thr2,
+                                                                          gmax, sp, up);
+                    else
+                        sweep_body<KS, C, MODE, false, true, true, true>(a, tp, x0, y0, ty, thr2,
+                                                                         gmax, sp, up);
+                    return;
+                }
+            } else if (a.W - (a.W % C) + 2 * C <= xs + S::SW) {
+                if (!ba) {
+                    if (!by)
+                        sweep_body<KS, C, MODE, false, false, true, true, false, true>(
+                            a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                    else
+                        sweep_body<KS, C, MODE, false, true, true, true, false, true>(
+                            a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                } else if constexpr (kHasBA) {
+                    if (!by)
+                        sweep_body<KS, C, MODE, false, false, true, true, true, true>(
+                            a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                    else
+                        sweep_body<KS, C, MODE, false, true, true, true, true, true>(
+                            a, tp, x0, y0, ty, thr2, gmax, sp, up);
+                }
+                return;
+            }
         }
     }
     if constexpr (kHasBL) {

@@ -6,7 +6,8 @@ multiple of 4) all run the vector sweep; a right edge whose straddling lane
 has no lane after it in the strip falls back to the per-element variant.
 Widths here put the edge at each position within a lane, in the second,
 third and fifth 248-column strip, and on both sides of that fallback
-(W = 494 keeps the vector path, 497 and 499 do not).  Each mask is compared
+(W = 494 keeps the vector path, 497 and 499 do not), and images narrower
+than one strip, whose two edges lie in the same strip.  Each mask is compared
 with the fp64 oracle, with the same image in dense buffers, and bytes
 outside the mask view must stay untouched; per image and batched, under
 every pass structure."""
@@ -24,7 +25,11 @@ from paper_2503_10855_amd import synth
 pytestmark = pytest.mark.gpu
 THETA = 0.1
 SHAPES = [(83, 757), (61, 998), (45, 1003), (70, 500), (40, 494), (40, 497),
-          (40, 499), (37, 1241), (29, 253)]
+          (40, 499), (37, 1241), (29, 253),
+          # narrower than one strip: both edges in it (k <= 5 keeps the
+          # vector path from W = 8 up to 245 + W % 4, 248 for W % 4 == 0)
+          (50, 61), (33, 130), (41, 247), (35, 248), (30, 245), (30, 249),
+          (20, 9), (20, 8), (20, 7)]
 SENTINEL = 7
 
 
@@ -56,7 +61,7 @@ def check_outside(buf, lead, w, what):
     assert np.all(b[:, lead + w:] == SENTINEL), what
 
 
-@pytest.mark.parametrize("ks,sigma", [(5, 1.0), (7, 1.5)])
+@pytest.mark.parametrize("ks,sigma", [(3, 0.8), (5, 1.0), (7, 1.5)])
 def test_unaligned_rows_and_ragged_right_edges(hx, ks, sigma):
     imgs = [synth.image(h, w, 61, i) for i, (h, w) in enumerate(SHAPES)]
     with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 4)) as ex:
