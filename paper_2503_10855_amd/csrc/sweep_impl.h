@@ -905,6 +905,17 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
                                               : src_al;
     const bool mask_al = ((reinterpret_cast<uintptr_t>(a.mask) % 4) == 0) & ((a.mp % 4) == 0);
     constexpr bool kHasBA = C == 4 && WRITES_MASK;
+    // The common case first: the tile's window lies inside the image and
+    // its rows are aligned (the same choice the checks below make for it,
+    // reached without evaluating them).
+    {
+        const bool by0 = (y0 - S::HY < 0) | (y0 + ty + S::HY > a.H);
+        if ((xs >= 0) & (xs + S::SW <= a.W) & src_al & (!WRITES_MASK || (C == 4 && mask_al)) &
+            !by0) {
+            sweep_body<KS, C, MODE, false, false>(a, tp, x0, y0, ty, thr2, gmax, sp, up);
+            return;
+        }
+    }
     const bool mask_vec = !WRITES_MASK || C == 4;
     const bool ba = kHasBA && !mask_al;
     const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
