@@ -148,13 +148,13 @@ struct BatchHeader {
 size_t batch_table_bytes(int n_images, int64_t n_items1, int64_t n_items2,
                          int64_t n_items0);
 // SPECULATE: pass-0 band geometry (8 sampled rows at the top of every
-// sample_stride(H) rows: every H/32 rows clamped to [128, 256], but at
-// least four bands in an image shorter than 512 rows) and the listed-pixel
+// sample_stride(H) rows: every H/32 rows clamped to [192, 256], but at
+// least four bands in an image shorter than 768 rows) and the listed-pixel
 // capacity of one pass-1 item, in entries.  Denser samples raise the bound
 // (fewer pixels for pass 2); thinner ones cost pass 0 less.
 constexpr int kSampleRows = 8;
 __host__ __device__ inline int sample_stride(int64_t H) {
-    const int64_t f = H / 32 < 128 ? 128 : (H / 32 > 256 ? 256 : H / 32);
+    const int64_t f = H / 32 < 192 ? 192 : (H / 32 > 256 ? 256 : H / 32);
     const int64_t q = H / 4 < 8 ? 8 : H / 4;
     return (int)(f < q ? f : q);
 }
