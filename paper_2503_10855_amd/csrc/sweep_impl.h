@@ -356,7 +356,8 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // Byte offsets of the lane's first column in an input / mask row.  Only
     // lanes inside the image (or, in the border variants, with clamped
     // columns) ever access memory through them.
-    static_assert(!BL || (!BX && C == 4 && S::HL == 4), "BL: one lane left of column 0");
+    static_assert(!BL || (!BX && C == 4 && (S::HL == 4 || S::HL == 8)),
+                  "BL: one or two lanes left of column 0");
     static_assert(!BR || (!BX && C == 4), "BR: whole lanes right of column W-1");
     static_assert(!BA || (!BX && (!BR || BQ) && C == 4 && (MODE == SM_MASK || MODE == SM_SPEC)),
                   "BA: vector rows with mask rows that are not word aligned");
@@ -384,7 +385,7 @@ __device__ __forceinline__ void sweep_body(const ImgArgs& a, const Taps& tp,
     // Lanes whose every column has a valid G^2 (its neighbourhood lies in
     // the strip); outside the border variants those are all real pixels.
     const bool gvalid = (cbase >= xs + R + 1) & (cbase + C <= xs + SW - R - 1) &
-                        (!BR || (BQ ? cbase < W : cbase + C <= W));
+                        (!BR || (BQ ? cbase < W : cbase + C <= W)) & (!BL || cbase >= 0);
     bool ecol[C];
 #pragma unroll
     for (int e = 0; e < C; ++e) ecol[e] = lane_out & (cbase + e < W);
@@ -920,8 +921,10 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
     const bool ba = kHasBA && !mask_al;
     const bool bx = (xs < 0) | (xs + S::SW > a.W) | !vec_ok | !mask_vec;
     // Left border only, vector rows: the vector path with the edge lane's
-    // values fixed (C = 4 and a one-lane left halo, i.e. k <= 5).
-    constexpr bool kHasBL = C == 4 && S::HL == 4;
+    // values fixed (C = 4 and a left halo of one lane, k <= 5, or two, k = 7:
+    // only the lane just left of column 0 reaches an output, since no stage
+    // reaches further than 3 columns and B and L at column -1 are fixed).
+    constexpr bool kHasBL = C == 4 && (S::HL == 4 || S::HL == 8);
     const bool bl = kHasBL && (xs < 0) & (xs + S::SW <= a.W) & vec_ok & mask_vec;
     // Right border only, 4C-byte aligned input rows, word-aligned mask rows
     // and a width that is a multiple of 4.
