@@ -957,8 +957,8 @@ __device__ __forceinline__ void sweep_tile(const ImgArgs& a, const Taps& tp,
             return;
         }
     }
-    // Both borders in one strip (an image narrower than the strip, k <= 5,
-    // modes that write no float plane): the left edge lane's fixes and the
+    // Both borders in one strip (an image narrower than the strip, modes
+    // that write no float plane): the left edge lane's fixes and the
     // right edge's together; they touch different lanes once W >= 2C.
     if constexpr (kHasBL && kHasBQ) {
         const bool bn = (xs < 0) & (xs + S::SW > a.W) & (a.W >= 2 * C) & vec_ok & mask_vec;

@@ -26,8 +26,8 @@ pytestmark = pytest.mark.gpu
 THETA = 0.1
 SHAPES = [(83, 757), (61, 998), (45, 1003), (70, 500), (40, 494), (40, 497),
           (40, 499), (37, 1241), (29, 253),
-          # narrower than one strip: both edges in it (k <= 5 keeps the
-          # vector path from W = 8 up to 245 + W % 4, 248 for W % 4 == 0)
+          # narrower than one strip: both edges in it (the vector path
+          # from W = 8 up to the width the strip's right edge allows)
           (50, 61), (33, 130), (41, 247), (35, 248), (30, 245), (30, 249),
           (20, 9), (20, 8), (20, 7)]
 SENTINEL = 7
